@@ -1,0 +1,30 @@
+"""FP64 CPU oracle for the closed-shell (T) energy correction.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link anything in this package: only the tests, the smoke check and the
+benchmark's CPU-baseline leg use it.  It shares no code with the HIP path;
+the only thing both sides use is the seeded input generator in ``synth``.
+
+Contents
+--------
+closed_shell
+    The closed-shell (T) energy as a plain loop over unique occupied
+    triples i <= j <= k (section 2.4.2 of the paper, Eqs. 2-7, with the
+    readings of its garbled equations listed in that module's docstring).
+spin_orbital
+    A brute-force spin-orbital (T) energy from the textbook definition
+    (Raghavachari et al. 1989; Crawford & Schaefer, Rev. Comp. Chem. 14,
+    2000), used only on tiny systems to pin the closed-shell oracle.
+
+Every function works in IEEE FP64.  Parity status: both functions are
+pinned (see tests/test_oracle_pins.py); no function here is "parity
+unpinned".
+"""
+from .closed_shell import (  # noqa: F401
+    t_energy,
+    triple_energy,
+    triple_table,
+    w_tensor,
+    v_tensor,
+)
+from .spin_orbital import spinorb_t_energy  # noqa: F401

@@ -1,0 +1,158 @@
+"""Seeded synthetic inputs for the closed-shell (T) energy.
+
+This module is shared by the oracle, the tests and the benchmark. It draws
+random density-fitting factors and orbital energies and forms from them the
+inputs the (T) step consumes: MO integrals in chemists' notation, MP1 doubles
+amplitudes and random singles. It contains none of the (T) arithmetic itself.
+
+Workload recipe (the paper benchmarks water clusters in cc-pVXZ bases, whose
+geometries and converged amplitudes are not available here; these seeded
+inputs of the same shape stand in for them):
+
+* B[Q,p,q] = (X + X^T)/2 with X[Q,p,q] ~ N(0, 0.05^2), n = nocc + nvir
+  orbitals (occupied first), Q over naux fitting functions;
+* eps_o ~ U[-2, -0.3] sorted ascending, eps_v ~ U[0.1, 3] sorted ascending;
+* t1 ~ N(0, 0.01^2);
+* (pq|rs) = sum_Q B[Q,p,q] B[Q,r,s]  (density-fitted integrals, the
+  paper's section on mean-field methods factorises the ERIs this way);
+* t2[i,j,a,b] = (ia|jb) / (eps_i + eps_j - eps_a - eps_b)  (MP1 amplitudes).
+
+Draw order per seed (fixed; changing it changes every stored value):
+X, eps_o, eps_v, t1, all from numpy.random.default_rng(seed).
+
+Array layouts (row-major, last index fastest) are those of the C ABI:
+  eps_o[nocc], eps_v[nvir], t1[nocc][nvir], t2[nocc][nocc][nvir][nvir],
+  ovvv[i][a][b][c] = (ia|bc), ooov[j][l][i][a] = (jl|ia),
+  ovov[i][a][j][b] = (ia|jb).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "TInputs",
+    "draw_factors",
+    "make_inputs",
+    "serving_stream",
+    "CONFIGS",
+]
+
+# Workloads: (nocc, nvir, naux, seed).  "small" finishes in the oracle in
+# well under a second; the others are the single-GPU measurement shapes.
+CONFIGS = {
+    "small": (6, 30, 120, 0),
+    "large_fragment": (32, 300, 1000, 0),
+    "precision_sweep": (24, 240, 800, 0),
+    "largest_fragment": (48, 480, 1600, 0),
+}
+
+
+@dataclass
+class TInputs:
+    nocc: int
+    nvir: int
+    eps_o: np.ndarray
+    eps_v: np.ndarray
+    t1: np.ndarray
+    t2: np.ndarray
+    ovvv: np.ndarray
+    ooov: np.ndarray
+    ovov: np.ndarray
+
+    def arrays(self):
+        """The seven input arrays in ABI argument order."""
+        return (self.eps_o, self.eps_v, self.t1, self.t2, self.ovvv, self.ooov, self.ovov)
+
+    def nbytes(self) -> int:
+        return sum(a.nbytes for a in self.arrays())
+
+
+def draw_factors(nocc: int, nvir: int, naux: int, seed: int):
+    """Draw (B, eps_o, eps_v, t1) in the fixed order."""
+    if nocc < 1 or nvir < 1 or naux < 1:
+        raise ValueError("nocc, nvir and naux must be positive")
+    rng = np.random.default_rng(seed)
+    n = nocc + nvir
+    x = rng.normal(0.0, 0.05, (naux, n, n))
+    b = 0.5 * (x + x.transpose(0, 2, 1))
+    del x
+    eps_o = np.sort(rng.uniform(-2.0, -0.3, nocc))
+    eps_v = np.sort(rng.uniform(0.1, 3.0, nvir))
+    t1 = rng.normal(0.0, 0.01, (nocc, nvir))
+    return b, eps_o, eps_v, t1
+
+
+def _integrals(b: np.ndarray, nocc: int):
+    """ovvv, ooov, ovov from the factors B (FP64, BLAS products over Q)."""
+    naux, n, _ = b.shape
+    nvir = n - nocc
+    b_oo = np.ascontiguousarray(b[:, :nocc, :nocc]).reshape(naux, nocc * nocc)
+    b_ov = np.ascontiguousarray(b[:, :nocc, nocc:]).reshape(naux, nocc * nvir)
+    b_vv = np.ascontiguousarray(b[:, nocc:, nocc:]).reshape(naux, nvir * nvir)
+    ovvv = (b_ov.T @ b_vv).reshape(nocc, nvir, nvir, nvir)
+    ooov = (b_oo.T @ b_ov).reshape(nocc, nocc, nocc, nvir)
+    ovov = (b_ov.T @ b_ov).reshape(nocc, nvir, nocc, nvir)
+    return ovvv, ooov, ovov
+
+
+def make_inputs(nocc: int, nvir: int, naux: int, seed: int) -> TInputs:
+    """Seeded FP64 inputs for one (T) solve (see the module docstring)."""
+    b, eps_o, eps_v, t1 = draw_factors(nocc, nvir, naux, seed)
+    ovvv, ooov, ovov = _integrals(b, nocc)
+    del b
+    denom = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
+             - eps_v[None, None, :, None] - eps_v[None, None, None, :])
+    t2 = np.ascontiguousarray(ovov.transpose(0, 2, 1, 3)) / denom
+    return TInputs(nocc, nvir, eps_o, eps_v, t1, t2,
+                   np.ascontiguousarray(ovvv), np.ascontiguousarray(ooov),
+                   np.ascontiguousarray(ovov))
+
+
+def serving_stream(n_requests: int = 256, seed: int = 4, rate: float | None = None):
+    """Fragment shapes for the serving workload.
+
+    nocc ~ U{8..40}, nvir = round(r * nocc) with r ~ U[6, 10],
+    naux = round(3.3 * (nocc + nvir)); fragment f uses seed 10000 + f.
+    Shapes come from default_rng(seed); arrival gaps come from a separate
+    default_rng(seed + 1) stream as standard exponentials scaled by 1/rate,
+    so the shapes do not depend on the rate.  Without a rate every request
+    arrives at t = 0 (closed loop).  Returns a list of dicts with nocc, nvir,
+    naux, seed, t_arrive.
+    """
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for f in range(n_requests):
+        nocc = int(rng.integers(8, 41))
+        r = float(rng.uniform(6.0, 10.0))
+        nvir = int(round(r * nocc))
+        naux = int(round(3.3 * (nocc + nvir)))
+        shapes.append(dict(nocc=nocc, nvir=nvir, naux=naux, seed=10000 + f))
+    gaps = np.random.default_rng(seed + 1).standard_exponential(n_requests)
+    t = 0.0
+    for f, s in enumerate(shapes):
+        if rate:
+            t += float(gaps[f]) / rate
+        s["t_arrive"] = t
+    return shapes
+
+
+def unique_triple_count(nocc: int) -> int:
+    """Number of occupied triples i<=j<=k with not i=j=k (a counting fact)."""
+    return nocc * (nocc + 1) * (nocc + 2) // 6 - nocc
+
+
+def flops_alg(nocc: int, nvir: int) -> float:
+    """Algorithmic flop count of one solve over unique triples.
+
+    Six permuted contraction terms per triple, each 2 v^4 (particle) +
+    2 o v^3 (hole) flops.
+    """
+    return 12.0 * unique_triple_count(nocc) * float(nvir) ** 3 * (nvir + nocc)
+
+
+def _check() -> None:  # pragma: no cover - tiny self check
+    x = make_inputs(2, 3, 4, 0)
+    assert math.isfinite(float(x.t2.sum()))
