@@ -1,0 +1,178 @@
+/*
+ * bqc.h - C ABI of the MI355X (gfx950) closed-shell (T) energy library.
+ *
+ * The library computes the perturbative-triples correction E_T of CCSD(T)
+ * for a closed-shell canonical Hartree-Fock reference (paper section 2.4.2,
+ * Eqs. 2-7): from the converged CCSD singles t1 and doubles t2, the orbital
+ * energies and the MO integrals (ia|bc), (ia|jl), (ia|jb) it returns one
+ * scalar.  Everything of the computation runs in HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * o = nocc >= 1 occupied, v = nvir >= 1 virtual spatial orbitals.  All arrays
+ * are dense, row-major (last index fastest), IEEE FP64:
+ *   eps_o [o]             occupied orbital energies e_i
+ *   eps_v [v]             virtual orbital energies e_a
+ *   t1    [o][v]          t_i^a
+ *   t2    [o][o][v][v]    t_ij^ab  (the caller guarantees t_ij^ab = t_ji^ba)
+ *   ovvv  [o][v][v][v]    (ia|bc)  chemists' notation, symmetric in b,c
+ *   ooov  [o][o][o][v]    ooov[j][l][i][a] = (jl|ia) = (ia|jl)
+ *   ovov  [o][v][o][v]    (ia|jb)
+ * Symmetries of the inputs are not checked.  The gap condition
+ * max(eps_o) < min(eps_v) is checked (it makes every energy denominator
+ * e_i + e_j + e_k - e_a - e_b - e_c negative); a violated gap, a non-finite
+ * orbital energy, a null pointer or a size below 1 returns BQC_EINVAL.
+ *
+ * Input buffers are borrowed, read-only and owned by the caller.  Outputs are
+ * written only when the call returns BQC_OK; on any error nothing is written.
+ * No C++ exception crosses this interface.  bqc_last_error() returns a
+ * thread-local message for the last non-OK return of the calling thread.
+ *
+ * Unique occupied triples: i <= j <= k without i = j = k, in lexicographic
+ * order of (i, j, k).  There are o(o+1)(o+2)/6 - o of them; their per-triple
+ * energies sum to E_T.
+ */
+#ifndef BQC_H
+#define BQC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BQC_OK         0
+#define BQC_PENDING    1   /* bqc_t_poll only: the request has not finished */
+#define BQC_EINVAL    -1   /* bad argument (see above) */
+#define BQC_ENOMEM    -2   /* request larger than the memory budget, or a device allocation failed */
+#define BQC_EDEVICE   -3   /* HIP runtime or kernel failure */
+#define BQC_ENOTFOUND -4   /* unknown or already consumed ticket */
+#define BQC_ESHUTDOWN -5   /* the server is shutting down */
+
+/* Arithmetic of the contractions (Eq. 2).  The energy denominator, the
+ * per-triple energy and the sum over triples are FP64 in every mode. */
+typedef enum {
+    BQC_PREC_FP64   = 0,  /* FP64 MFMA, FP64 accumulation */
+    BQC_PREC_FP32   = 1,  /* FP32 operands, FP32 MFMA accumulation */
+    BQC_PREC_BF16X3 = 2,  /* split x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 accumulation */
+    BQC_PREC_FP8    = 3   /* FP8 e4m3 operands with a power-of-two scale per 32 contraction elements */
+} bqc_precision;
+
+/*
+ * Synchronous single solve (paper Eqs. 2-7): host input pointers, FP64
+ * contractions, device 0, the library's own stream.  Writes *E_T on success.
+ */
+int bqc_t_energy(int32_t nocc, int32_t nvir,
+                 const double* eps_o, const double* eps_v,
+                 const double* t1, const double* t2,
+                 const double* ovvv, const double* ooov, const double* ovov,
+                 double* E_T);
+
+/* Options of bqc_t_energy_ex.  A zero-initialised struct means: FP64,
+ * device 0, host inputs, library stream, no per-triple output. */
+typedef struct {
+    int32_t precision;        /* bqc_precision */
+    int32_t device;           /* HIP device ordinal */
+    int32_t inputs_on_device; /* 1: the seven input pointers are device pointers on `device`,
+                                 readable in stream order on `stream` */
+    int32_t timing;           /* 1: record per-kernel HIP events and fill the kernel fields of stats */
+    void*   stream;           /* hipStream_t to run on, or NULL for the library's stream of `device` */
+    double* triple_energies;  /* NULL, or a HOST array of bqc_t_num_triples(nocc) doubles that receives
+                                 the per-triple energies e_ijk in unique-triple order */
+} bqc_t_opts;
+
+/* Per-solve measurements.  Times are seconds. */
+typedef struct {
+    double   queue_s;      /* serving: submit -> admission */
+    double   upload_s;     /* host -> device copies (0 for device inputs) */
+    double   prepare_s;    /* layout and precision conversion of the inputs (HIP events) */
+    double   gpu_s;        /* first kernel start -> final reduction end (HIP events) */
+    double   total_s;      /* wall time of the call (serving: submit -> completion) */
+    double   flops;        /* algorithmic flops 12 * n_triples * v^3 * (v + o) */
+    double   gemm_s;       /* timing=1: summed duration of the contraction kernel launches */
+    double   epilogue_s;   /* timing=1: summed duration of the epilogue kernel launches */
+    uint64_t footprint_bytes; /* device memory the solve held */
+    int32_t  gemm_launches;
+    int32_t  epilogue_launches;
+    int32_t  precision;
+    int32_t  n_triples;
+} bqc_t_stats;
+
+/*
+ * Single solve with options (see bqc_t_opts).  Returns when *E_T is known
+ * (the stream is synchronised).  stats may be NULL.
+ */
+int bqc_t_energy_ex(int32_t nocc, int32_t nvir,
+                    const double* eps_o, const double* eps_v,
+                    const double* t1, const double* t2,
+                    const double* ovvv, const double* ooov, const double* ovov,
+                    const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats);
+
+/* Number of unique occupied triples for nocc (0 for nocc < 1). */
+int64_t bqc_t_num_triples(int32_t nocc);
+
+/* Device bytes one solve of this shape and precision holds (its footprint,
+ * inputs included), or -1 for invalid arguments. */
+int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision);
+
+/* ---------------------------------------------------------------- serving
+ * A server owns one device, a memory budget and a scheduler thread.  Each
+ * request is one independent (T) solve (an embedding fragment).  Requests
+ * are admitted in arrival order as soon as the in-flight count and the
+ * memory budget allow; admitted requests run concurrently on the device.
+ * A request's result is bitwise identical to bqc_t_energy_ex at the same
+ * precision on the same device: its decomposition and reduction order depend
+ * only on (nocc, nvir, precision).
+ */
+typedef struct bqc_server bqc_server;
+
+typedef struct {
+    int32_t  device;           /* HIP device ordinal */
+    int32_t  precision;        /* bqc_precision for every request */
+    uint64_t mem_budget_bytes; /* 0: 85% of the device's free memory at creation */
+    int32_t  max_inflight;     /* 0: 4 */
+    int32_t  n_streams;        /* 0: max_inflight */
+} bqc_server_cfg;
+
+/* Creates a server; *out is written on BQC_OK. */
+int bqc_server_create(const bqc_server_cfg* cfg, bqc_server** out);
+
+/* Cancels queued requests (they never run), waits for admitted ones, frees
+ * every device buffer, every ticket and the server.  No ticket of the server
+ * may be polled afterwards. */
+int bqc_server_destroy(bqc_server* s);
+
+/*
+ * Enqueues one solve with HOST input pointers.  The buffers are borrowed
+ * until bqc_t_poll returns a terminal status for the ticket.  A request whose
+ * footprint exceeds the budget is rejected here with BQC_ENOMEM and never
+ * queued.  *ticket is written on BQC_OK.  Thread-safe.
+ */
+int bqc_t_submit(bqc_server* s, int32_t nocc, int32_t nvir,
+                 const double* eps_o, const double* eps_v,
+                 const double* t1, const double* t2,
+                 const double* ovvv, const double* ooov, const double* ovov,
+                 uint64_t* ticket);
+
+/*
+ * Non-blocking status of a ticket: BQC_PENDING while queued or running;
+ * BQC_OK with *E_T (and *stats if non-NULL) written once it finished; a
+ * negative code if the request failed.  A terminal return consumes the
+ * ticket (a later poll returns BQC_ENOTFOUND).  Thread-safe.
+ */
+int bqc_t_poll(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats);
+
+/* Blocking variant of bqc_t_poll (waits until the ticket is terminal). */
+int bqc_t_wait(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats);
+
+/* Thread-local message of the calling thread's last non-OK return. */
+const char* bqc_last_error(void);
+
+/* ABI version: major * 10000 + minor * 100 + patch. */
+int32_t bqc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BQC_H */

@@ -1,0 +1,20 @@
+"""MI355X (gfx950) closed-shell (T) energy: HIP kernels behind a C ABI.
+
+The computation lives in libbqc.so (built from csrc/ by ``build.py``); this
+package holds only the ctypes binding of include/bqc.h.
+"""
+from .binding import (  # noqa: F401
+    BqcError,
+    Server,
+    PRECISIONS,
+    footprint,
+    header_functions,
+    last_error,
+    lib,
+    num_triples,
+    t_energy,
+    t_energy_plain,
+)
+
+__all__ = ["BqcError", "Server", "PRECISIONS", "footprint", "header_functions", "last_error", "lib",
+           "num_triples", "t_energy", "t_energy_plain"]

@@ -1,0 +1,252 @@
+"""ctypes binding of libbqc.so (include/bqc.h).
+
+Argument marshalling only: every step of the (T) computation runs in the HIP
+kernels behind the C ABI.  Inputs may be numpy FP64 arrays (host; the
+library uploads them) or torch FP64 tensors on a HIP device (passed as device
+pointers on the current torch stream).  If the library is not built the
+first call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbqc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bqc.h")
+
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOTFOUND, ESHUTDOWN = 0, 1, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp8": 3}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class TOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("inputs_on_device", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("triple_energies", _dp)]
+
+
+class TStats(ctypes.Structure):
+    _fields_ = [("queue_s", ctypes.c_double), ("upload_s", ctypes.c_double),
+                ("prepare_s", ctypes.c_double), ("gpu_s", ctypes.c_double),
+                ("total_s", ctypes.c_double), ("flops", ctypes.c_double),
+                ("gemm_s", ctypes.c_double), ("epilogue_s", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_uint64), ("gemm_launches", ctypes.c_int32),
+                ("epilogue_launches", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_triples", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32)]
+
+
+class BqcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bqc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Load libbqc.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "python -m paper_2502_17963_amd.build")
+            # One HIP runtime per process: torch's wheel ships its own
+            # libamdhip64 (soname libamdhip64.so.7).  Loading torch first lets
+            # the dynamic loader bind libbqc.so to that same runtime instead of
+            # bringing in a second one, which torch could then not initialise.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
+            L = ctypes.CDLL(LIB_PATH)
+            seven = [_dp] * 7
+            L.bqc_t_energy.argtypes = [ctypes.c_int32, ctypes.c_int32, *seven, _dp]
+            L.bqc_t_energy.restype = ctypes.c_int
+            L.bqc_t_energy_ex.argtypes = [ctypes.c_int32, ctypes.c_int32, *seven,
+                                          ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
+            L.bqc_t_energy_ex.restype = ctypes.c_int
+            L.bqc_t_num_triples.argtypes = [ctypes.c_int32]
+            L.bqc_t_num_triples.restype = ctypes.c_int64
+            L.bqc_t_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+            L.bqc_t_footprint.restype = ctypes.c_int64
+            L.bqc_last_error.argtypes = []
+            L.bqc_last_error.restype = ctypes.c_char_p
+            L.bqc_version.argtypes = []
+            L.bqc_version.restype = ctypes.c_int32
+            if hasattr(L, "bqc_server_create"):
+                L.bqc_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
+                L.bqc_server_create.restype = ctypes.c_int
+                L.bqc_server_destroy.argtypes = [ctypes.c_void_p]
+                L.bqc_server_destroy.restype = ctypes.c_int
+                L.bqc_t_submit.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, *seven,
+                                           ctypes.POINTER(ctypes.c_uint64)]
+                L.bqc_t_submit.restype = ctypes.c_int
+                L.bqc_t_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _dp, ctypes.POINTER(TStats)]
+                L.bqc_t_poll.restype = ctypes.c_int
+                L.bqc_t_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _dp, ctypes.POINTER(TStats)]
+                L.bqc_t_wait.restype = ctypes.c_int
+            _lib = L
+        return _lib
+
+
+def header_functions():
+    """Names of the functions include/bqc.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\*?\s+\*?(bqc_[a-z0-9_]+)\s*\(", text, re.M)))
+
+
+def last_error() -> str:
+    return lib().bqc_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise BqcError(rc, last_error())
+
+
+def num_triples(nocc: int) -> int:
+    return int(lib().bqc_t_num_triples(nocc))
+
+
+def footprint(nocc: int, nvir: int, precision="fp64") -> int:
+    return int(lib().bqc_t_footprint(nocc, nvir, _prec(precision)))
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _ptrs(arrays):
+    """(pointers, on_device, keepalive) for numpy arrays or torch tensors."""
+    first = arrays[0]
+    if isinstance(first, np.ndarray):
+        keep = [np.ascontiguousarray(a, dtype=np.float64) for a in arrays]
+        return [k.ctypes.data_as(_dp) for k in keep], False, keep
+    # torch tensors on a HIP device
+    for a in arrays:
+        if a.dtype.itemsize != 8 or not a.is_contiguous() or not a.is_cuda:
+            raise ValueError("device inputs must be contiguous float64 tensors on a HIP device")
+    return [ctypes.cast(ctypes.c_void_p(a.data_ptr()), _dp) for a in arrays], True, list(arrays)
+
+
+def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64",
+             device=0, triple_energies=False, timing=False, stream=None, stats=False):
+    """E_T through bqc_t_energy_ex.
+
+    Returns E_T, or (E_T, extras) when triple_energies or stats is requested;
+    extras holds "triples" (numpy array in unique-triple order) and/or "stats".
+    """
+    arrays = (eps_o, eps_v, t1, t2, ovvv, ooov, ovov)
+    ptrs, on_dev, keep = _ptrs(arrays)
+    opts = TOpts()
+    opts.precision = _prec(precision)
+    opts.device = device
+    opts.inputs_on_device = 1 if on_dev else 0
+    opts.timing = 1 if timing else 0
+    if stream is not None:
+        opts.stream = ctypes.c_void_p(stream)
+    elif on_dev:
+        import torch
+        opts.stream = ctypes.c_void_p(torch.cuda.current_stream(arrays[0].device).cuda_stream)
+    etrip = None
+    if triple_energies:
+        etrip = np.zeros(max(num_triples(nocc), 1))
+        opts.triple_energies = etrip.ctypes.data_as(_dp)
+    e = ctypes.c_double(0.0)
+    st = TStats()
+    rc = lib().bqc_t_energy_ex(nocc, nvir, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
+    del keep
+    _check(rc)
+    if not (triple_energies or stats or timing):
+        return e.value
+    extras = {}
+    if triple_energies:
+        extras["triples"] = etrip[:num_triples(nocc)]
+    extras["stats"] = st.as_dict()
+    return e.value, extras
+
+
+def t_energy_plain(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov):
+    """E_T through bqc_t_energy (host inputs, FP64, device 0)."""
+    ptrs, on_dev, keep = _ptrs((eps_o, eps_v, t1, t2, ovvv, ooov, ovov))
+    if on_dev:
+        raise ValueError("bqc_t_energy takes host arrays")
+    e = ctypes.c_double(0.0)
+    rc = lib().bqc_t_energy(nocc, nvir, *ptrs, ctypes.byref(e))
+    del keep
+    _check(rc)
+    return e.value
+
+
+class Server:
+    """bqc_server_* wrapper: continuous batching of independent (T) solves.
+
+    Host input arrays are kept alive until the ticket reaches a terminal
+    status (the C ABI borrows them until then).
+    """
+
+    def __init__(self, precision="fp64", device=0, mem_budget_bytes=0, max_inflight=0):
+        cfg = ServerCfg()
+        cfg.device = device
+        cfg.precision = _prec(precision)
+        cfg.mem_budget_bytes = int(mem_budget_bytes)
+        cfg.max_inflight = int(max_inflight)
+        self._h = ctypes.c_void_p()
+        _check(lib().bqc_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov) -> int:
+        ptrs, on_dev, keep = _ptrs((eps_o, eps_v, t1, t2, ovvv, ooov, ovov))
+        if on_dev:
+            raise ValueError("bqc_t_submit takes host arrays")
+        t = ctypes.c_uint64()
+        _check(lib().bqc_t_submit(self._h, nocc, nvir, *ptrs, ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def _finish(self, fn, ticket):
+        e = ctypes.c_double()
+        st = TStats()
+        rc = fn(self._h, ticket, ctypes.byref(e), ctypes.byref(st))
+        if rc == PENDING:
+            return None
+        self._keep.pop(ticket, None)
+        _check(rc)
+        return e.value, st.as_dict()
+
+    def poll(self, ticket):
+        """None while pending, else (E_T, stats); raises BqcError on failure."""
+        return self._finish(lib().bqc_t_poll, ticket)
+
+    def wait(self, ticket):
+        return self._finish(lib().bqc_t_wait, ticket)
+
+    def close(self):
+        if self._h:
+            _check(lib().bqc_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,242 @@
+// extern "C" entry points of include/bqc.h: argument validation, device
+// context pool, host<->device copies and error translation.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bqc.h"
+#include "bqc_internal.h"
+
+namespace bqc {
+
+double* workspace_etrip(void* ws, int o, int v, int precision);
+double* workspace_energy(void* ws, int o, int v, int precision);
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+// Validates sizes, pointers, finiteness of the orbital energies and the gap.
+int validate(int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v, const double* t1,
+             const double* t2, const double* ovvv, const double* ooov, const double* ovov,
+             bool host_eps) {
+    if (nocc < 1 || nvir < 1) return fail(BQC_EINVAL, "nocc and nvir must be >= 1");
+    if (nocc > 4096 || nvir > 8192) return fail(BQC_EINVAL, "nocc or nvir beyond the supported range");
+    if (!eps_o || !eps_v || !t1 || !t2 || !ovvv || !ooov || !ovov)
+        return fail(BQC_EINVAL, "null input pointer");
+    if (!host_eps) return BQC_OK;
+    double omax = -INFINITY, vmin = INFINITY;
+    for (int i = 0; i < nocc; ++i) {
+        if (!std::isfinite(eps_o[i])) return fail(BQC_EINVAL, "non-finite occupied orbital energy");
+        omax = std::max(omax, eps_o[i]);
+    }
+    for (int a = 0; a < nvir; ++a) {
+        if (!std::isfinite(eps_v[a])) return fail(BQC_EINVAL, "non-finite virtual orbital energy");
+        vmin = std::min(vmin, eps_v[a]);
+    }
+    if (!(omax < vmin)) return fail(BQC_EINVAL, "gap condition max(eps_o) < min(eps_v) violated");
+    return BQC_OK;
+}
+
+// ------------------------------------------------------------------ context pool
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;
+    size_t ws_size = 0;
+    void* in = nullptr;
+    size_t in_size = 0;
+    double* host_energy = nullptr;  // pinned 8 bytes
+    bool busy = false;
+};
+
+std::mutex g_pool_mu;
+std::vector<Ctx*> g_pool;
+
+Ctx* acquire_ctx(int device) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (Ctx* c : g_pool)
+        if (!c->busy && c->device == device) { c->busy = true; return c; }
+    Ctx* c = new Ctx();
+    c->device = device;
+    c->busy = true;
+    g_pool.push_back(c);
+    return c;
+}
+void release_ctx(Ctx* c) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    c->busy = false;
+}
+
+void ensure(void*& p, size_t& have, size_t need) {
+    if (have >= need && p) return;
+    if (p) { BQC_HIP(hipFree(p)); p = nullptr; have = 0; }
+    BQC_HIP(hipMalloc(&p, std::max<size_t>(need, 256)));
+    have = std::max<size_t>(need, 256);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        BQC_HIP(hipGetDevice(&prev));
+        if (prev != dev) BQC_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, const double* t1,
+               const double* t2, const double* ovvv, const double* ooov, const double* ovov,
+               const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats) {
+    bqc_t_opts op;
+    std::memset(&op, 0, sizeof(op));
+    if (opts) op = *opts;
+    if (!E_T) return fail(BQC_EINVAL, "E_T is null");
+    if (op.precision < 0 || op.precision > 3) return fail(BQC_EINVAL, "unknown precision");
+    const bool dev_in = op.inputs_on_device != 0;
+    int rc = validate(o, v, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, !dev_in);
+    if (rc != BQC_OK) return rc;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BQC_EDEVICE, "no HIP device");
+    if (op.device < 0 || op.device >= ndev) return fail(BQC_EINVAL, "device ordinal out of range");
+
+    auto wall0 = std::chrono::steady_clock::now();
+    DeviceGuard dg(op.device);
+    Ctx* ctx = acquire_ctx(op.device);
+    struct Rel { Ctx* c; ~Rel() { release_ctx(c); } } rel{ctx};
+    if (!ctx->stream) BQC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    if (!ctx->host_energy) BQC_HIP(hipHostMalloc((void**)&ctx->host_energy, 256, hipHostMallocDefault));
+    hipStream_t st = op.stream ? (hipStream_t)op.stream : ctx->stream;
+
+    if (dev_in) {  // check the orbital energies from a host copy
+        std::vector<double> eo(o), evv(v);
+        BQC_HIP(hipMemcpyAsync(eo.data(), eps_o, o * sizeof(double), hipMemcpyDeviceToHost, st));
+        BQC_HIP(hipMemcpyAsync(evv.data(), eps_v, v * sizeof(double), hipMemcpyDeviceToHost, st));
+        BQC_HIP(hipStreamSynchronize(st));
+        rc = validate(o, v, eo.data(), evv.data(), t1, t2, ovvv, ooov, ovov, true);
+        if (rc != BQC_OK) return rc;
+    }
+
+    const int64_t ntrip = num_triples(o);
+    const size_t sizes[7] = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v,
+                             (size_t)o * v * v * v, (size_t)o * o * o * v, (size_t)o * v * o * v};
+    DevInputs in;
+    in.o = o;
+    in.v = v;
+    double upload_s = 0.0;
+    if (dev_in) {
+        in.eps_o = eps_o; in.eps_v = eps_v; in.t1 = t1; in.t2 = t2;
+        in.ovvv = ovvv; in.ooov = ooov; in.ovov = ovov;
+    } else {
+        size_t need = 0;
+        for (size_t s : sizes) need += a256(s * sizeof(double));
+        ensure(ctx->in, ctx->in_size, need);
+        const double* src[7] = {eps_o, eps_v, t1, t2, ovvv, ooov, ovov};
+        const double* dst[7];
+        char* p = (char*)ctx->in;
+        auto u0 = std::chrono::steady_clock::now();
+        for (int a = 0; a < 7; ++a) {
+            BQC_HIP(hipMemcpyAsync(p, src[a], sizes[a] * sizeof(double), hipMemcpyHostToDevice, st));
+            dst[a] = (const double*)p;
+            p += a256(sizes[a] * sizeof(double));
+        }
+        BQC_HIP(hipStreamSynchronize(st));
+        upload_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - u0).count();
+        in.eps_o = dst[0]; in.eps_v = dst[1]; in.t1 = dst[2]; in.t2 = dst[3];
+        in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
+    }
+
+    const Plan plan = make_plan(o, v, op.precision);
+    ensure(ctx->ws, ctx->ws_size, (size_t)workspace_bytes(o, v, op.precision));
+    SolveStats ss;
+    enqueue_solve(plan, in, ctx->ws, nullptr, st, op.timing != 0, stats ? &ss : nullptr);
+    BQC_HIP(hipMemcpyAsync(ctx->host_energy, workspace_energy(ctx->ws, o, v, op.precision), sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    std::vector<double> etrip;
+    if (op.triple_energies && ntrip > 0) {
+        etrip.resize(ntrip);
+        BQC_HIP(hipMemcpyAsync(etrip.data(), workspace_etrip(ctx->ws, o, v, op.precision),
+                               ntrip * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    BQC_HIP(hipStreamSynchronize(st));
+    const double e = *ctx->host_energy;
+    if (!std::isfinite(e)) return fail(BQC_EDEVICE, "non-finite energy (device arithmetic failed)");
+    *E_T = e;
+    if (op.triple_energies && ntrip > 0) std::memcpy(op.triple_energies, etrip.data(), ntrip * sizeof(double));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->upload_s = upload_s;
+        stats->prepare_s = ss.prepare_s;
+        stats->gpu_s = ss.gpu_s;
+        stats->gemm_s = ss.gemm_s;
+        stats->epilogue_s = ss.epi_s;
+        stats->gemm_launches = ss.gemm_launches;
+        stats->epilogue_launches = ss.epi_launches;
+        stats->footprint_bytes = ss.footprint + (dev_in ? 0 : (uint64_t)input_bytes(o, v));
+        stats->flops = 12.0 * (double)ntrip * (double)v * v * v * (double)(v + o);
+        stats->precision = op.precision;
+        stats->n_triples = (int32_t)ntrip;
+        stats->total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+    }
+    return BQC_OK;
+}
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(BQC_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(BQC_EDEVICE, e.what());
+    } catch (...) {
+        return fail(BQC_EDEVICE, "unknown failure");
+    }
+}
+
+}  // namespace bqc
+
+using namespace bqc;
+
+extern "C" {
+
+int bqc_t_energy(int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v,
+                 const double* t1, const double* t2, const double* ovvv, const double* ooov,
+                 const double* ovov, double* E_T) {
+    return guarded([&] {
+        return solve_impl(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, nullptr, E_T, nullptr);
+    });
+}
+
+int bqc_t_energy_ex(int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v,
+                    const double* t1, const double* t2, const double* ovvv, const double* ooov,
+                    const double* ovov, const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats) {
+    return guarded([&] {
+        return solve_impl(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, opts, E_T, stats);
+    });
+}
+
+int64_t bqc_t_num_triples(int32_t nocc) { return num_triples(nocc); }
+
+int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision) {
+    if (nocc < 1 || nvir < 1 || precision < 0 || precision > 3) return -1;
+    return workspace_bytes(nocc, nvir, precision) + input_bytes(nocc, nvir);
+}
+
+const char* bqc_last_error(void) { return g_last_error.c_str(); }
+
+int32_t bqc_version(void) { return 100; }
+
+}  // extern "C"

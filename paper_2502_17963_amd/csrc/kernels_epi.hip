@@ -1,0 +1,211 @@
+// Fused FP64 epilogue of the (T) energy and the deterministic reductions
+// (paper section 2.4.2, Eqs. 3-4 and 6-7; the denominator is formed in
+// registers from the orbital energies, as the paper's in-place denominator
+// kernel does, and no rank-6 or rank-3 denominator tensor exists).
+//
+// For one occupied triple (i, j, k) of weight m and a tile orbit
+// {A, B, C} (A >= B >= C, tiles of EPI_T virtuals), the work group builds in
+// LDS, for the six tile permutations s(A, B, C),
+//   W = H_a[a][b][c] + H_b[b][a][c] + H_c[c][a][b]            (six-fold P)
+//   V = W + t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)       (singles term)
+// and every thread takes one element (a, b, c) of the base tile with its
+// six permutations p.  With D = e_i + e_j + e_k - e_a - e_b - e_c (the same
+// for all six) the numerator operator 4 + cyclic - 2 transpositions acting on
+// V gives, for even p:  3 V_p + S_e - 2 S_o  and for odd p:  3 V_p + S_o - 2 S_e
+// (S_e, S_o = sums of V over even and odd permutations), so
+//   sum_p W_p Z_p = [3 sum_p W_p V_p + (S_e - 2 S_o) W_e + (S_o - 2 S_e) W_o] / D.
+// Summing this over the base tile counts every element of the orbit's tiles
+// |stabiliser(A, B, C)| times, which the work group divides out.  Padding
+// elements (index >= v) have W = 0 and contribute nothing.
+//
+// No floating-point atomics: each work group writes one FP64 partial; the
+// partials are summed per triple and then over triples in a fixed order with
+// Neumaier compensation.
+#include "bqc_internal.h"
+
+namespace bqc {
+namespace {
+
+constexpr int E_T3 = EPI_T * EPI_T * EPI_T;
+constexpr int E_THREADS = 256;
+static_assert(E_T3 % E_THREADS == 0, "tile elements divide over threads");
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <typename HT>
+__global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
+    const int orb = blockIdx.x, t = blockIdx.y;
+    const int4 ob = e.orbits[orb];
+    const int4 tr = e.trip[t];
+    const int i = tr.x, j = tr.y, k = tr.z;
+    const int v = e.v;
+    const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
+    const HT* Ha = (const HT*)e.hbuf + (int64_t)(t * 3 + 0) * v3;
+    const HT* Hb = Ha + v3;
+    const HT* Hc = Hb + v3;
+    const double* t1i = e.t1 + (int64_t)i * v;
+    const double* t1j = e.t1 + (int64_t)j * v;
+    const double* t1k = e.t1 + (int64_t)k * v;
+    // (jb|kc) = ovov[j][b][k][c] etc.: row stride o*v within the j block
+    const int64_t ov = (int64_t)e.o * v;
+    const double* g_jk = e.ovov + (int64_t)j * v * ov + (int64_t)k * v;
+    const double* g_ik = e.ovov + (int64_t)i * v * ov + (int64_t)k * v;
+    const double* g_ij = e.ovov + (int64_t)i * v * ov + (int64_t)j * v;
+
+    __shared__ double Ws[6][E_T3];
+    __shared__ double Vs[6][E_T3];
+    __shared__ double red[E_THREADS / 64];
+
+    // tile permutations: 0 (A,B,C) 1 (A,C,B) 2 (B,A,C) 3 (B,C,A) 4 (C,A,B) 5 (C,B,A)
+    const int TA = ob.x, TB = ob.y, TC = ob.z;
+    const int tiles[6][3] = {{TA, TB, TC}, {TA, TC, TB}, {TB, TA, TC},
+                             {TB, TC, TA}, {TC, TA, TB}, {TC, TB, TA}};
+
+    // pass 1: z-fastest threads read H_a and H_b (contiguous in c) and add the singles term
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
+            const int x = el / (EPI_T * EPI_T), y = (el / EPI_T) % EPI_T, z = el % EPI_T;
+            const int a = tiles[s][0] * EPI_T + x, b = tiles[s][1] * EPI_T + y,
+                      c = tiles[s][2] * EPI_T + z;
+            double w = 0.0, vv = 0.0;
+            if (a < v && b < v && c < v) {
+                w = (double)Ha[(int64_t)a * v2 + (int64_t)b * v + c] +
+                    (double)Hb[(int64_t)b * v2 + (int64_t)a * v + c];
+                vv = w + t1i[a] * g_jk[(int64_t)b * ov + c] + t1j[b] * g_ik[(int64_t)a * ov + c] +
+                     t1k[c] * g_ij[(int64_t)a * ov + b];
+            }
+            Ws[s][el] = w;
+            Vs[s][el] = vv;
+        }
+    }
+    __syncthreads();
+    // pass 2: b-fastest threads read H_c[c][a][b] (contiguous in b)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
+            const int x = el / (EPI_T * EPI_T), z = (el / EPI_T) % EPI_T, y = el % EPI_T;
+            const int a = tiles[s][0] * EPI_T + x, b = tiles[s][1] * EPI_T + y,
+                      c = tiles[s][2] * EPI_T + z;
+            if (a < v && b < v && c < v) {
+                const double hc = (double)Hc[(int64_t)c * v2 + (int64_t)a * v + b];
+                const int li = (x * EPI_T + y) * EPI_T + z;
+                Ws[s][li] += hc;
+                Vs[s][li] += hc;
+            }
+        }
+    }
+    __syncthreads();
+
+    const double eocc = e.eps_o[i] + e.eps_o[j] + e.eps_o[k];
+    double acc = 0.0;
+    for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
+        const int al = el / (EPI_T * EPI_T), be = (el / EPI_T) % EPI_T, ga = el % EPI_T;
+        const int a = TA * EPI_T + al, b = TB * EPI_T + be, c = TC * EPI_T + ga;
+        if (a >= v || b >= v || c >= v) continue;
+        const int T2 = EPI_T * EPI_T;
+        // element (a,b,c) and its permutations in the six tiles
+        const int idx[6] = {(al * EPI_T + be) * EPI_T + ga,   // (a,b,c) in (A,B,C)
+                            (al * EPI_T + ga) * EPI_T + be,   // (a,c,b) in (A,C,B)
+                            (be * EPI_T + al) * EPI_T + ga,   // (b,a,c) in (B,A,C)
+                            (be * EPI_T + ga) * EPI_T + al,   // (b,c,a) in (B,C,A)
+                            ga * T2 + al * EPI_T + be,        // (c,a,b) in (C,A,B)
+                            ga * T2 + be * EPI_T + al};       // (c,b,a) in (C,B,A)
+        double W[6], V[6];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            W[p] = Ws[p][idx[p]];
+            V[p] = Vs[p][idx[p]];
+        }
+        const double d = eocc - e.eps_v[a] - e.eps_v[b] - e.eps_v[c];
+        const double se = V[0] + V[3] + V[4], so = V[1] + V[2] + V[5];
+        const double we = W[0] + W[3] + W[4], wo = W[1] + W[2] + W[5];
+        double wv = 0.0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) wv += W[p] * V[p];
+        const double num = 3.0 * wv + (se - 2.0 * so) * we + (so - 2.0 * se) * wo;
+        acc += num / d;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < E_THREADS / 64; ++w) s += red[w];
+        e.partial[(int64_t)t * e.norbit + orb] = s / (double)ob.w;
+    }
+}
+
+// Neumaier compensated accumulation: (s, c) += x
+__device__ __forceinline__ void neu_add(double& s, double& c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+constexpr int R_THREADS = 256;
+
+// Fixed-order compensated sum of n values at stride 1; block-wide result in thread 0.
+__device__ double block_sum_fixed(const double* x, int64_t n) {
+    __shared__ double ss[R_THREADS], cs[R_THREADS];
+    double s = 0.0, c = 0.0;
+    for (int64_t idx = threadIdx.x; idx < n; idx += R_THREADS) neu_add(s, c, x[idx]);
+    ss[threadIdx.x] = s;
+    cs[threadIdx.x] = c;
+    __syncthreads();
+    for (int half = R_THREADS / 2; half >= 1; half >>= 1) {
+        if (threadIdx.x < half) {
+            double s1 = ss[threadIdx.x], c1 = cs[threadIdx.x];
+            neu_add(s1, c1, ss[threadIdx.x + half]);
+            c1 += cs[threadIdx.x + half];
+            ss[threadIdx.x] = s1;
+            cs[threadIdx.x] = c1;
+        }
+        __syncthreads();
+    }
+    return ss[0] + cs[0];
+}
+
+__global__ __launch_bounds__(R_THREADS) void reduce_triples_kernel(const double* partial, int norbit,
+                                                                     const int4* trip, double* e_trip) {
+    const int t = blockIdx.x;
+    const double s = block_sum_fixed(partial + (int64_t)t * norbit, norbit);
+    if (threadIdx.x == 0) e_trip[t] = s * (double)trip[t].w / 3.0;
+}
+
+__global__ __launch_bounds__(R_THREADS) void reduce_total_kernel(const double* e_trip, int64_t n,
+                                                                   double* out) {
+    const double s = block_sum_fixed(e_trip, n);
+    if (threadIdx.x == 0) *out = s;
+}
+
+}  // namespace
+
+void launch_epilogue(int precision, const EpiLaunch& e, hipStream_t st) {
+    if (e.ntrip > 65535) throw Error(-1, "epilogue batch too large");
+    dim3 grid(e.norbit, e.ntrip), block(E_THREADS);
+    if (precision == 0)
+        hipLaunchKernelGGL(epilogue_kernel<double>, grid, block, 0, st, e);
+    else
+        hipLaunchKernelGGL(epilogue_kernel<float>, grid, block, 0, st, e);
+    BQC_HIP(hipGetLastError());
+}
+
+void launch_reduce_triples(const double* partial, int ntrip, int norbit, const int4* trip,
+                           double* e_trip, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_triples_kernel, dim3(ntrip), dim3(R_THREADS), 0, st, partial, norbit,
+                       trip, e_trip);
+    BQC_HIP(hipGetLastError());
+}
+
+void launch_reduce_total(const double* e_trip, int64_t n, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_total_kernel, dim3(1), dim3(R_THREADS), 0, st, e_trip, n, out);
+    BQC_HIP(hipGetLastError());
+}
+
+}  // namespace bqc

@@ -1,0 +1,389 @@
+// Continuous-batching (T) server (bqc_server_* / bqc_t_submit / bqc_t_poll).
+//
+// Each request is one independent (T) solve of an embedding fragment (the
+// fragments of the paper's embedding layer are independent problems).  The
+// server owns:
+//   * one device arena of mem_budget_bytes, allocated once at creation and
+//     carved first-fit per request (inputs + workspace), so the serving loop
+//     never calls hipMalloc/hipFree;
+//   * max_inflight slot threads, each with its own HIP stream.  An idle slot
+//     admits the oldest queued request whose footprint fits into the arena
+//     (a request may be overtaken by smaller ones at most kMaxBypass times,
+//     after which admission waits for it), uploads it, enqueues its whole
+//     solve on its stream and waits for it, so that admitted requests run
+//     concurrently on the device while new ones keep arriving.
+// A request's launch sequence is the one bqc_t_energy_ex uses, so its result
+// is bitwise identical alone and in the mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "../../include/bqc.h"
+#include "bqc_internal.h"
+
+namespace bqc {
+
+int fail(int code, const std::string& msg);
+int validate(int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v, const double* t1,
+             const double* t2, const double* ovvv, const double* ooov, const double* ovov,
+             bool host_eps);
+double* workspace_energy(void* ws, int o, int v, int precision);
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+constexpr int kMaxBypass = 32;
+inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// First-fit allocator over [0, size) with coalescing of free ranges.
+class Arena {
+  public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    bool alloc(size_t n, size_t* off) {
+        n = a256(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, start = it->first + n;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = a256(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
+};
+
+enum class St { Queued, Running, Done };
+
+struct Request {
+    uint64_t ticket = 0;
+    int o = 0, v = 0;
+    const double* src[7] = {};
+    St state = St::Queued;
+    int rc = BQC_PENDING;
+    std::string err;
+    double energy = 0.0;
+    bqc_t_stats stats{};
+    clk::time_point t_submit, t_admit;
+    size_t bytes = 0, off = 0;
+    int bypassed = 0;
+};
+
+}  // namespace
+}  // namespace bqc
+
+struct bqc_server {
+    int device = 0, precision = 0, max_inflight = 4;
+    uint64_t budget = 0;
+    void* arena_base = nullptr;
+    bqc::Arena* arena = nullptr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<bqc::Request*> queue;
+    std::unordered_map<uint64_t, bqc::Request*> reqs;
+    std::vector<std::thread> slots;
+    std::vector<hipStream_t> streams;
+    std::vector<double*> pinned;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+};
+
+namespace bqc {
+namespace {
+
+size_t request_bytes(int o, int v, int precision) {
+    return a256((size_t)input_bytes(o, v)) + a256((size_t)workspace_bytes(o, v, precision));
+}
+
+// Runs one admitted request on the slot's stream; returns the BQC code.
+int run_request(bqc_server* s, Request* r, hipStream_t st, double* pinned) {
+    const int o = r->o, v = r->v;
+    char* base = (char*)s->arena_base + r->off;
+    const size_t sizes[7] = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v,
+                             (size_t)o * v * v * v, (size_t)o * o * o * v, (size_t)o * v * o * v};
+    const double* dst[7];
+    char* p = base;
+    const auto u0 = clk::now();
+    for (int a = 0; a < 7; ++a) {
+        BQC_HIP(hipMemcpyAsync(p, r->src[a], sizes[a] * sizeof(double), hipMemcpyHostToDevice, st));
+        dst[a] = (const double*)p;
+        p += a256(sizes[a] * sizeof(double));
+    }
+    BQC_HIP(hipStreamSynchronize(st));
+    const double upload_s = std::chrono::duration<double>(clk::now() - u0).count();
+    void* ws = base + a256((size_t)input_bytes(o, v));
+    DevInputs in;
+    in.o = o; in.v = v;
+    in.eps_o = dst[0]; in.eps_v = dst[1]; in.t1 = dst[2]; in.t2 = dst[3];
+    in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
+    const Plan plan = make_plan(o, v, s->precision);
+    SolveStats ss;
+    enqueue_solve(plan, in, ws, nullptr, st, false, &ss);
+    BQC_HIP(hipMemcpyAsync(pinned, workspace_energy(ws, o, v, s->precision), sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    BQC_HIP(hipStreamSynchronize(st));
+    if (!std::isfinite(*pinned)) throw Error(BQC_EDEVICE, "non-finite energy");
+    r->energy = *pinned;
+    r->stats.upload_s = upload_s;
+    r->stats.prepare_s = ss.prepare_s;
+    r->stats.gpu_s = ss.gpu_s;
+    r->stats.footprint_bytes = r->bytes;
+    r->stats.flops = 12.0 * (double)num_triples(o) * (double)v * v * v * (double)(v + o);
+    r->stats.precision = s->precision;
+    r->stats.n_triples = (int32_t)num_triples(o);
+    return BQC_OK;
+}
+
+// Picks the request to admit (caller holds s->mu); nullptr if none fits.
+Request* admit_locked(bqc_server* s) {
+    for (size_t q = 0; q < s->queue.size(); ++q) {
+        Request* r = s->queue[q];
+        size_t off = 0;
+        if (s->arena->alloc(r->bytes, &off)) {
+            r->off = off;
+            for (size_t b = 0; b < q; ++b) s->queue[b]->bypassed++;
+            s->queue.erase(s->queue.begin() + q);
+            return r;
+        }
+        if (r->bypassed >= kMaxBypass) return nullptr;  // no overtaking a starved request
+    }
+    return nullptr;
+}
+
+void slot_main(bqc_server* s, int idx) {
+    (void)hipSetDevice(s->device);
+    hipStream_t st = s->streams[idx];
+    double* pinned = s->pinned[idx];
+    for (;;) {
+        Request* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (;;) {
+                if (s->stop && s->queue.empty()) return;
+                r = admit_locked(s);
+                if (r) break;
+                s->cv_work.wait(lk);
+            }
+            r->state = St::Running;
+            r->t_admit = clk::now();
+        }
+        int rc;
+        std::string err;
+        try {
+            rc = run_request(s, r, st, pinned);
+        } catch (const Error& e) {
+            rc = e.code;
+            err = e.what();
+        } catch (const std::exception& e) {
+            rc = BQC_EDEVICE;
+            err = e.what();
+        }
+        if (rc != BQC_OK) (void)hipStreamSynchronize(st);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->arena->release(r->off, r->bytes);
+            const auto now = clk::now();
+            r->stats.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
+            r->stats.total_s = std::chrono::duration<double>(now - r->t_submit).count();
+            r->rc = rc;
+            r->err = err;
+            r->state = St::Done;
+        }
+        s->cv_work.notify_all();  // freed memory may admit queued requests
+        s->cv_done.notify_all();
+    }
+}
+
+int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
+    if (!cfg || !out) return fail(BQC_EINVAL, "null argument");
+    if (cfg->precision < 0 || cfg->precision > 3) return fail(BQC_EINVAL, "unknown precision");
+    if (cfg->max_inflight < 0 || cfg->max_inflight > 64) return fail(BQC_EINVAL, "max_inflight out of range");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BQC_EDEVICE, "no HIP device");
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(BQC_EINVAL, "device ordinal out of range");
+    int prev = 0;
+    BQC_HIP(hipGetDevice(&prev));
+    BQC_HIP(hipSetDevice(cfg->device));
+    auto* s = new bqc_server();
+    s->device = cfg->device;
+    s->precision = cfg->precision;
+    s->max_inflight = cfg->max_inflight > 0 ? cfg->max_inflight : 4;
+    try {
+        size_t fr = 0, tot = 0;
+        BQC_HIP(hipMemGetInfo(&fr, &tot));
+        s->budget = cfg->mem_budget_bytes ? cfg->mem_budget_bytes : (uint64_t)(0.85 * (double)fr);
+        s->budget &= ~(uint64_t)255;
+        BQC_HIP(hipMalloc(&s->arena_base, s->budget));
+        s->arena = new Arena(s->budget);
+        for (int k = 0; k < s->max_inflight; ++k) {
+            hipStream_t st;
+            BQC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            s->streams.push_back(st);
+            double* p = nullptr;
+            BQC_HIP(hipHostMalloc((void**)&p, 256, hipHostMallocDefault));
+            s->pinned.push_back(p);
+        }
+    } catch (...) {
+        (void)hipSetDevice(prev);
+        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        for (double* p : s->pinned) (void)hipHostFree(p);
+        if (s->arena_base) (void)hipFree(s->arena_base);
+        delete s->arena;
+        delete s;
+        throw;
+    }
+    for (int k = 0; k < s->max_inflight; ++k) s->slots.emplace_back(slot_main, s, k);
+    (void)hipSetDevice(prev);
+    *out = s;
+    return BQC_OK;
+}
+
+int destroy_impl(bqc_server* s) {
+    if (!s) return fail(BQC_EINVAL, "null server");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Request* r : s->queue) {
+            r->rc = BQC_ESHUTDOWN;
+            r->state = St::Done;
+        }
+        s->queue.clear();
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& th : s->slots) th.join();
+    s->cv_done.notify_all();
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    for (double* p : s->pinned) (void)hipHostFree(p);
+    (void)hipFree(s->arena_base);
+    (void)hipSetDevice(prev);
+    for (auto& kv : s->reqs) delete kv.second;
+    delete s->arena;
+    delete s;
+    return BQC_OK;
+}
+
+int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7], uint64_t* ticket) {
+    if (!s || !ticket) return fail(BQC_EINVAL, "null argument");
+    int rc = validate(o, v, src[0], src[1], src[2], src[3], src[4], src[5], src[6], true);
+    if (rc != BQC_OK) return rc;
+    const size_t bytes = request_bytes(o, v, s->precision);
+    if (bytes > s->budget)
+        return fail(BQC_ENOMEM, "request footprint " + std::to_string(bytes) + " B exceeds the budget " +
+                                    std::to_string(s->budget) + " B");
+    auto* r = new Request();
+    r->o = o;
+    r->v = v;
+    for (int a = 0; a < 7; ++a) r->src[a] = src[a];
+    r->bytes = bytes;
+    r->t_submit = clk::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            delete r;
+            return fail(BQC_ESHUTDOWN, "server is shutting down");
+        }
+        r->ticket = s->next_ticket++;
+        s->reqs[r->ticket] = r;
+        s->queue.push_back(r);
+    }
+    s->cv_work.notify_all();
+    *ticket = r->ticket;
+    return BQC_OK;
+}
+
+int poll_impl(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats, bool wait) {
+    if (!s) return fail(BQC_EINVAL, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(BQC_ENOTFOUND, "unknown or consumed ticket");
+    Request* r = it->second;
+    if (wait) s->cv_done.wait(lk, [&] { return r->state == St::Done; });
+    if (r->state != St::Done) return BQC_PENDING;
+    const int rc = r->rc;
+    if (rc == BQC_OK) {
+        if (E_T) *E_T = r->energy;
+        if (stats) *stats = r->stats;
+    } else {
+        fail(rc, r->err.empty() ? "request failed" : r->err);
+    }
+    s->reqs.erase(it);
+    delete r;
+    return rc;
+}
+
+template <typename F>
+int guarded_srv(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(BQC_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(BQC_EDEVICE, e.what());
+    } catch (...) {
+        return fail(BQC_EDEVICE, "unknown failure");
+    }
+}
+
+}  // namespace
+}  // namespace bqc
+
+using namespace bqc;
+
+extern "C" {
+
+int bqc_server_create(const bqc_server_cfg* cfg, bqc_server** out) {
+    return guarded_srv([&] { return create_impl(cfg, out); });
+}
+
+int bqc_server_destroy(bqc_server* s) {
+    return guarded_srv([&] { return destroy_impl(s); });
+}
+
+int bqc_t_submit(bqc_server* s, int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v,
+                 const double* t1, const double* t2, const double* ovvv, const double* ooov,
+                 const double* ovov, uint64_t* ticket) {
+    const double* src[7] = {eps_o, eps_v, t1, t2, ovvv, ooov, ovov};
+    return guarded_srv([&] { return submit_impl(s, nocc, nvir, src, ticket); });
+}
+
+int bqc_t_poll(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats) {
+    return guarded_srv([&] { return poll_impl(s, ticket, E_T, stats, false); });
+}
+
+int bqc_t_wait(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats) {
+    return guarded_srv([&] { return poll_impl(s, ticket, E_T, stats, true); });
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Host driver of one (T) solve: the triple and tile-orbit tables, the
+// workspace layout and the launch sequence
+//   prepare (a1) -> per triple batch: contraction, epilogue, per-triple sum
+//   -> compensated sum over triples.
+#include <algorithm>
+#include <chrono>
+
+#include "bqc_internal.h"
+
+namespace bqc {
+
+void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st);
+void launch_gemm_lowp(int precision, const GemmLaunch& g, hipStream_t st);
+
+void launch_gemm(int precision, const GemmLaunch& g, hipStream_t st) {
+    if (precision == 0 || precision == 1) launch_gemm_fp(precision, g, st);
+    else launch_gemm_lowp(precision, g, st);
+}
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Device memory the H buffers of one batch may take.
+constexpr int64_t kHBudget = (int64_t)1 << 30;
+
+struct Layout {
+    size_t ops, trip, orbits, hbuf, partial, etrip, energy, total;
+};
+
+Layout layout(int o, int v, int precision) {
+    const int nb = batch_triples(o, v, precision);
+    const int nt = ceil_div(v, EPI_T);
+    const int64_t norbit = num_tile_orbits(nt);
+    const int64_t ntrip = num_triples(o);
+    const int64_t v3 = (int64_t)v * v * v;
+    Layout L;
+    size_t off = 0;
+    L.ops = off; off += align256(prepare_bytes(precision, o, v));
+    L.trip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(int4));
+    L.orbits = off; off += align256((size_t)norbit * sizeof(int4));
+    L.hbuf = off; off += align256((size_t)nb * 3 * v3 * hbuf_bytes(precision));
+    L.partial = off; off += align256((size_t)nb * norbit * sizeof(double));
+    L.etrip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(double));
+    L.energy = off; off += 256;
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+int batch_triples(int o, int v, int precision) {
+    const int64_t per = 3 * (int64_t)v * v * v * hbuf_bytes(precision);
+    int64_t nb = kHBudget / std::max<int64_t>(per, 1);
+    nb = std::max<int64_t>(nb, 1);
+    nb = std::min<int64_t>(nb, std::max<int64_t>(num_triples(o), 1));
+    nb = std::min<int64_t>(nb, 4096);
+    return (int)nb;
+}
+
+int64_t workspace_bytes(int o, int v, int precision) { return (int64_t)layout(o, v, precision).total; }
+
+int64_t input_bytes(int o, int v) {
+    const int64_t n = (int64_t)o + v + (int64_t)o * v + (int64_t)o * o * v * v +
+                      (int64_t)o * v * v * v + (int64_t)o * o * o * v + (int64_t)o * v * o * v;
+    return n * 8 + 7 * 256;
+}
+
+Plan make_plan(int o, int v, int precision) {
+    Plan p;
+    p.o = o;
+    p.v = v;
+    p.precision = precision;
+    p.nb = batch_triples(o, v, precision);
+    for (int i = 0; i < o; ++i)
+        for (int j = i; j < o; ++j)
+            for (int k = j; k < o; ++k) {
+                if (i == j && j == k) continue;
+                const int m = (i < j && j < k) ? 6 : 3;
+                p.trip.push_back(make_int4(i, j, k, m));
+            }
+    const int nt = ceil_div(v, EPI_T);
+    for (int A = 0; A < nt; ++A)
+        for (int B = 0; B <= A; ++B)
+            for (int C = 0; C <= B; ++C) {
+                const int stab = (A == B && B == C) ? 6 : ((A == B || B == C) ? 2 : 1);
+                p.orbits.push_back(make_int4(A, B, C, stab));
+            }
+    return p;
+}
+
+void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
+                   hipStream_t st, bool timing, SolveStats* stats) {
+    const int o = plan.o, v = plan.v, prec = plan.precision;
+    const Layout L = layout(o, v, prec);
+    char* base = (char*)ws;
+    int4* d_trip = (int4*)(base + L.trip);
+    int4* d_orb = (int4*)(base + L.orbits);
+    void* hbuf = base + L.hbuf;
+    double* partial = (double*)(base + L.partial);
+    double* etrip = (double*)(base + L.etrip);
+    const int ntrip = (int)plan.trip.size();
+    const int norbit = (int)plan.orbits.size();
+
+    std::vector<hipEvent_t> ev;
+    auto mark = [&](bool on) -> hipEvent_t {
+        if (!on) return nullptr;
+        hipEvent_t e;
+        BQC_HIP(hipEventCreate(&e));
+        BQC_HIP(hipEventRecord(e, st));
+        ev.push_back(e);
+        return e;
+    };
+    if (!stats) timing = false;
+    const bool want = stats != nullptr;
+    hipEvent_t e_begin = mark(want);
+
+    if (ntrip > 0)
+        BQC_HIP(hipMemcpyAsync(d_trip, plan.trip.data(), plan.trip.size() * sizeof(int4),
+                               hipMemcpyHostToDevice, st));
+    BQC_HIP(hipMemcpyAsync(d_orb, plan.orbits.data(), plan.orbits.size() * sizeof(int4),
+                           hipMemcpyHostToDevice, st));
+    Operands ops;
+    if (ntrip > 0) launch_prepare(prec, in, base + L.ops, &ops, st);
+    hipEvent_t e_prep = mark(want);
+
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm_ev, epi_ev;
+    for (int b0 = 0; b0 < ntrip; b0 += plan.nb) {
+        const int nb = std::min(plan.nb, ntrip - b0);
+        GemmLaunch g;
+        g.o = o; g.v = v; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf;
+        hipEvent_t g0 = mark(timing);
+        launch_gemm(prec, g, st);
+        hipEvent_t g1 = mark(timing);
+        if (timing) gemm_ev.emplace_back(g0, g1);
+        EpiLaunch e;
+        e.o = o; e.v = v; e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf;
+        e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
+        e.orbits = d_orb; e.norbit = norbit; e.partial = partial;
+        hipEvent_t p0 = mark(timing);
+        launch_epilogue(prec, e, st);
+        hipEvent_t p1 = mark(timing);
+        if (timing) epi_ev.emplace_back(p0, p1);
+        launch_reduce_triples(partial, nb, norbit, d_trip + b0, etrip + b0, st);
+    }
+    launch_reduce_total(etrip, ntrip, (double*)(base + L.energy), st);
+    if (d_energy)
+        BQC_HIP(hipMemcpyAsync(d_energy, base + L.energy, sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipEvent_t e_end = mark(want);
+
+    if (stats) {
+        BQC_HIP(hipEventSynchronize(e_end));
+        float ms = 0;
+        BQC_HIP(hipEventElapsedTime(&ms, e_begin, e_prep));
+        stats->prepare_s = ms * 1e-3;
+        BQC_HIP(hipEventElapsedTime(&ms, e_begin, e_end));
+        stats->gpu_s = ms * 1e-3;
+        double gs = 0, es = 0;
+        for (auto& pr : gemm_ev) { BQC_HIP(hipEventElapsedTime(&ms, pr.first, pr.second)); gs += ms * 1e-3; }
+        for (auto& pr : epi_ev) { BQC_HIP(hipEventElapsedTime(&ms, pr.first, pr.second)); es += ms * 1e-3; }
+        stats->gemm_s = gs;
+        stats->epi_s = es;
+        stats->gemm_launches = (int)gemm_ev.size();
+        stats->epi_launches = (int)epi_ev.size();
+        stats->footprint = L.total;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+// Device pointer of the per-triple energies and the total inside a workspace.
+double* workspace_etrip(void* ws, int o, int v, int precision) {
+    return (double*)((char*)ws + layout(o, v, precision).etrip);
+}
+double* workspace_energy(void* ws, int o, int v, int precision) {
+    return (double*)((char*)ws + layout(o, v, precision).energy);
+}
+
+}  // namespace bqc

@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library loads, exports every function include/bqc.h declares, and the
+argument checks that precede any device work return the documented codes.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2502_17963_amd as bqc
+from paper_2502_17963_amd import binding
+from synth import make_inputs
+
+
+def test_library_exports_every_declared_function():
+    L = bqc.lib()
+    names = bqc.header_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/bqc.h but not exported"
+
+
+def test_version_and_counts():
+    L = bqc.lib()
+    assert L.bqc_version() >= 100
+    for o in range(0, 9):
+        expect = max(o * (o + 1) * (o + 2) // 6 - o, 0)
+        assert bqc.num_triples(o) == expect
+    assert bqc.footprint(0, 10) == -1 and bqc.footprint(3, 0) == -1
+    assert bqc.footprint(4, 20, "fp64") > 0
+
+
+def test_footprint_grows_with_size_and_shrinks_with_precision():
+    f64 = bqc.footprint(32, 300, "fp64")
+    f32 = bqc.footprint(32, 300, "fp32")
+    assert f64 > 8 * 32 * 300 ** 3  # holds at least the FP64 (ia|bc)
+    assert bqc.footprint(32, 320, "fp64") > f64
+    assert f32 > 0
+
+
+def _call(o, v, arrays, E=True, precision=0):
+    ptrs = [None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrays]
+    e = ctypes.c_double(123.0)
+    opts = binding.TOpts()
+    opts.precision = precision
+    rc = bqc.lib().bqc_t_energy_ex(o, v, *ptrs, ctypes.byref(opts), ctypes.byref(e) if E else None, None)
+    return rc, e.value
+
+
+def test_invalid_sizes_and_pointers():
+    x = make_inputs(3, 5, 10, 0)
+    arr = list(x.arrays())
+    assert _call(0, 5, arr)[0] == binding.EINVAL
+    assert _call(3, 0, arr)[0] == binding.EINVAL
+    for k in range(7):
+        bad = list(arr)
+        bad[k] = None
+        rc, e = _call(3, 5, bad)
+        assert rc == binding.EINVAL and e == 123.0  # output untouched on error
+    assert _call(3, 5, arr, E=False)[0] == binding.EINVAL
+    assert _call(3, 5, arr, precision=7)[0] == binding.EINVAL
+    assert "precision" in bqc.last_error()
+
+
+def test_gap_and_finiteness_checks():
+    x = make_inputs(3, 5, 10, 0)
+    eo = x.eps_o.copy()
+    eo[-1] = x.eps_v[0]  # max occupied == min virtual: no gap
+    rc, e = _call(3, 5, [eo, *x.arrays()[1:]])
+    assert rc == binding.EINVAL and e == 123.0
+    assert "gap" in bqc.last_error()
+    ev = x.eps_v.copy()
+    ev[2] = np.nan
+    rc, _ = _call(3, 5, [x.eps_o, ev, *x.arrays()[2:]])
+    assert rc == binding.EINVAL and "finite" in bqc.last_error()
+
+
+def test_server_argument_checks():
+    L = bqc.lib()
+    out = ctypes.c_void_p()
+    assert L.bqc_server_create(None, ctypes.byref(out)) == binding.EINVAL
+    cfg = binding.ServerCfg()
+    cfg.precision = 9
+    assert L.bqc_server_create(ctypes.byref(cfg), ctypes.byref(out)) == binding.EINVAL
+    assert L.bqc_server_destroy(None) == binding.EINVAL
+    t = ctypes.c_uint64()
+    assert L.bqc_t_poll(None, 1, None, None) == binding.EINVAL
+    x = make_inputs(2, 3, 6, 0)
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in x.arrays()]
+    assert L.bqc_t_submit(None, 2, 3, *ptrs, ctypes.byref(t)) == binding.EINVAL

@@ -1,0 +1,130 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 contractions: |E_gpu - E_oracle| <= 1e-10 |E_oracle| (and every
+per-triple energy within 1e-10 of the largest one).  Mixed precision:
+|dE| <= 1 uEh on the small workload and relative error <= 1e-6 elsewhere
+(the synthetic energies grow far beyond 1 Eh at the larger shapes, where
+1 uEh is below the FP64 oracle's own rounding).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth import make_inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+FP64_REL = 1e-10
+
+
+def _bqc():
+    import paper_2502_17963_amd as bqc
+    bqc.lib()
+    return bqc
+
+
+def _case(o, v, naux, seed):
+    for c in GOLDEN["cases"]:
+        if (c["nocc"], c["nvir"], c["naux"], c["seed"]) == (o, v, naux, seed):
+            return c
+    raise KeyError((o, v, naux, seed))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_small_fp64_matches_oracle(seed):
+    bqc = _bqc()
+    print(f"case small seed={seed}", flush=True)
+    x = make_inputs(6, 30, 120, seed)
+    ref = _case(6, 30, 120, seed)["E_T"]
+    e = bqc.t_energy(6, 30, *x.arrays(), precision="fp64")
+    assert abs(e - ref) <= FP64_REL * abs(ref), (e, ref)
+
+
+def test_small_fp64_per_triple():
+    bqc = _bqc()
+    x = make_inputs(6, 30, 120, 0)
+    ref = np.array(_case(6, 30, 120, 0)["triples"])
+    e, ex = bqc.t_energy(6, 30, *x.arrays(), triple_energies=True)
+    got = ex["triples"]
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= FP64_REL * np.max(np.abs(ref))
+    assert abs(e - float(np.sum(ref))) <= FP64_REL * abs(e)
+
+
+RAGGED = [(2, 17, 40, 5), (5, 37, 100, 3), (7, 45, 150, 2), (3, 1, 12, 4), (1, 9, 20, 6),
+          (9, 20, 60, 8), (4, 64, 160, 1)]
+
+
+@pytest.mark.parametrize("o,v,naux,seed", RAGGED)
+def test_ragged_fp64(o, v, naux, seed):
+    bqc = _bqc()
+    print(f"case ragged o={o} v={v} seed={seed}", flush=True)
+    x = make_inputs(o, v, naux, seed)
+    ref = _case(o, v, naux, seed)["E_T"]
+    e = bqc.t_energy(o, v, *x.arrays())
+    scale = max(abs(ref), 1e-30)
+    if o == 1:
+        assert e == 0.0
+    elif v == 1:
+        assert abs(e) <= 1e-12 * np.max(np.abs(x.ovvv)) ** 2 * np.max(np.abs(x.t2)) ** 2
+    else:
+        assert abs(e - ref) <= FP64_REL * scale, (e, ref)
+
+
+def test_plain_entry_equals_ex_entry_bitwise():
+    bqc = _bqc()
+    x = make_inputs(5, 37, 100, 3)
+    a = bqc.t_energy_plain(5, 37, *x.arrays())
+    b = bqc.t_energy(5, 37, *x.arrays(), precision="fp64")
+    assert a == b
+
+
+def test_deterministic_repeat():
+    bqc = _bqc()
+    x = make_inputs(7, 45, 150, 2)
+    a = bqc.t_energy(7, 45, *x.arrays())
+    b = bqc.t_energy(7, 45, *x.arrays())
+    assert a == b
+
+
+def test_device_inputs_equal_host_inputs():
+    import torch
+    bqc = _bqc()
+    x = make_inputs(6, 30, 120, 4)
+    host = bqc.t_energy(6, 30, *x.arrays())
+    dev = [torch.from_numpy(a).to("cuda:0") for a in x.arrays()]
+    e = bqc.t_energy(6, 30, *dev)
+    torch.cuda.synchronize()
+    assert e == host
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_small_fp32(seed):
+    bqc = _bqc()
+    x = make_inputs(6, 30, 120, seed)
+    ref = _case(6, 30, 120, seed)["E_T"]
+    e = bqc.t_energy(6, 30, *x.arrays(), precision="fp32")
+    print(f"fp32 seed={seed} dE={abs(e - ref) * 1e6:.3e} uEh", flush=True)
+    assert abs(e - ref) <= 1e-6
+
+
+def test_ragged_fp32():
+    bqc = _bqc()
+    for (o, v, naux, seed) in [(5, 37, 100, 3), (9, 20, 60, 8), (4, 64, 160, 1)]:
+        x = make_inputs(o, v, naux, seed)
+        ref = _case(o, v, naux, seed)["E_T"]
+        e = bqc.t_energy(o, v, *x.arrays(), precision="fp32")
+        assert abs(e - ref) <= 1e-6 * abs(ref), (o, v, e, ref)
+
+
+def test_invalid_arguments_rejected():
+    bqc = _bqc()
+    x = make_inputs(3, 5, 10, 0)
+    bad = x.eps_o.copy()
+    bad[-1] = x.eps_v[0] + 0.1  # gap violated
+    with pytest.raises(bqc.BqcError) as ei:
+        bqc.t_energy(3, 5, bad, *x.arrays()[1:])
+    assert ei.value.code == -1
