@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "(T) TFLOP/s at |ΔE_T|≤1 µEh vs FP64; fragment req/s + p50/p99 latency"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp8": 5000.0}
 MIXED_REL_GATE = 1e-6
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
 
 def parse():
@@ -34,13 +35,23 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large_fragment",
-                    choices=["small", "large_fragment", "precision_sweep", "largest_fragment"])
+                    choices=["small", "large_fragment", "precision_sweep", "largest_fragment", "serving",
+                             "copy_calibration"])
     ap.add_argument("--precisions", default="fp32",
                     help="comma list of candidate contraction precisions for the headline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--out", default=None, help="also write the JSON line to this file")
+    ap.add_argument("--requests", type=int, default=64,
+                    help="serving workload: first N fragments of the 256-fragment stream")
+    ap.add_argument("--serving-precision", default="bf16x3")
+    ap.add_argument("--inflight", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=100.0, help="serving arena size")
+    ap.add_argument("--input-cap-gb", type=float, default=80.0,
+                    help="serving: device memory allowed for generated-but-unfinished fragment inputs")
+    ap.add_argument("--rate-frac", type=float, default=0.7,
+                    help="serving open loop: arrival rate as a fraction of the closed-loop req/s (0: skip)")
     return ap.parse_args()
 
 
@@ -101,8 +112,128 @@ def _blas_threads() -> int:
     return os.cpu_count() or 1
 
 
+def _serve_stream(bqc, srv, shapes, arrivals, cap_bytes, keep_idx):
+    """Submit fragments at their arrival times (generated on the GPU when they
+    arrive, as long as the outstanding inputs fit cap_bytes), poll to
+    completion.  Returns per-request records and the makespan."""
+    import torch
+
+    from synth import make_inputs_device
+    t0 = time.perf_counter()
+    pending, rec, kept = {}, {}, {}
+    nxt, outstanding = 0, 0
+    while len(rec) < len(shapes):
+        now = time.perf_counter() - t0
+        while nxt < len(shapes) and arrivals[nxt] <= now:
+            sh = shapes[nxt]
+            nbytes = 8 * (sh["nocc"] * sh["nvir"] ** 3 + 2 * sh["nocc"] ** 2 * sh["nvir"] ** 2
+                          + sh["nocc"] ** 3 * sh["nvir"])
+            if pending and outstanding + nbytes > cap_bytes:
+                break
+            x = make_inputs_device(sh["nocc"], sh["nvir"], sh["naux"], sh["seed"])
+            t = srv.submit(sh["nocc"], sh["nvir"], *x)
+            pending[t] = (nxt, x, nbytes, time.perf_counter() - t0)
+            outstanding += nbytes
+            nxt += 1
+        done = []
+        for t, (i, x, nbytes, t_sub) in pending.items():
+            r = srv.poll(t)
+            if r is not None:
+                t_done = time.perf_counter() - t0
+                e, st = r
+                rec[i] = {"E_T": e, "latency_s": t_done - arrivals[i], "service_s": st["total_s"],
+                          "queue_s": st["queue_s"], "gpu_s": st["gpu_s"], "submit_s": t_sub,
+                          "flops": st["flops"]}
+                if i in keep_idx:
+                    kept[i] = x
+                done.append(t)
+                outstanding -= nbytes
+        for t in done:
+            del pending[t]
+        if done:
+            torch.cuda.empty_cache()
+        elif nxt >= len(shapes) or arrivals[nxt] > now:
+            time.sleep(0.002)
+    return rec, time.perf_counter() - t0, kept
+
+
+def run_serving(args):
+    import numpy as np
+    import torch
+
+    import paper_2502_17963_amd as bqc
+    from synth import flops_alg, serving_stream
+
+    shapes = serving_stream(256)[:args.requests]
+    F = np.array([flops_alg(s["nocc"], s["nvir"]) for s in shapes])
+    prec = args.serving_precision
+    keep_idx = set(int(i) for i in np.argsort(F)[:3])  # three smallest: re-solved alone
+    out = {"metric": METRIC, "unit": "req/s", "n_gpus": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": prec,
+           "data": "synthetic fragments generated on the GPU (torch device RNG, same recipe)",
+           "config": {"workload": "serving", "requests": len(shapes), "of_stream": 256,
+                      "precision": prec, "max_inflight": args.inflight, "arena_gb": args.budget_gb}}
+    with bqc.Server(precision=prec, max_inflight=args.inflight,
+                    mem_budget_bytes=int(args.budget_gb * 1e9)) as srv:
+        cap = args.input_cap_gb * 1e9
+        rec, span, kept = _serve_stream(bqc, srv, shapes, [0.0] * len(shapes), cap, keep_idx)
+        closed_rps = len(shapes) / span
+        lat = np.array([rec[i]["latency_s"] for i in range(len(shapes))])
+        out["closed_loop"] = {"req_s": round(closed_rps, 4), "makespan_s": round(span, 2),
+                              "tflops": round(F.sum() / span / 1e12, 2),
+                              "p50_s": round(float(np.percentile(lat, 50)), 3),
+                              "p99_s": round(float(np.percentile(lat, 99)), 3)}
+        print(f"[serving] closed loop {len(shapes)} req in {span:.1f} s: {closed_rps:.3f} req/s, "
+              f"{F.sum() / span / 1e12:.1f} TFLOP/s", file=sys.stderr, flush=True)
+        # alone vs in the mix, bitwise
+        same = []
+        for i, x in kept.items():
+            sh = shapes[i]
+            e = bqc.t_energy(sh["nocc"], sh["nvir"], *x, precision=prec)
+            torch.cuda.synchronize()
+            same.append(e == rec[i]["E_T"])
+        out["alone_equals_mix"] = {"checked": len(same), "bitwise_equal": int(sum(same))}
+        value = closed_rps
+        if args.rate_frac > 0:
+            rate = args.rate_frac * closed_rps
+            arr = [s["t_arrive"] for s in serving_stream(256, rate=rate)[:args.requests]]
+            rec2, span2, _ = _serve_stream(bqc, srv, shapes, arr, cap, set())
+            lat2 = np.array([rec2[i]["latency_s"] for i in range(len(shapes))])
+            out["open_loop"] = {"rate_req_s": round(rate, 4), "req_s": round(len(shapes) / span2, 4),
+                                "makespan_s": round(span2, 2),
+                                "p50_s": round(float(np.percentile(lat2, 50)), 3),
+                                "p99_s": round(float(np.percentile(lat2, 99)), 3),
+                                "tflops": round(F.sum() / span2 / 1e12, 2)}
+            print(f"[serving] open loop at {rate:.3f} req/s: p50 {out['open_loop']['p50_s']} s "
+                  f"p99 {out['open_loop']['p99_s']} s", file=sys.stderr, flush=True)
+    out["value"] = round(value, 4)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+def run_copy_calibration(args):
+    """A plain device copy of known size: the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters (each launch reads and writes exactly
+    COPY_BYTES)."""
+    import torch
+    n = COPY_BYTES // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(max(args.steps, 1)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": max(args.steps, 1)}), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "serving" and args.gpus == 1:
+        return run_serving(args)
+    if args.workload == "copy_calibration":
+        return run_copy_calibration(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding of the "
                           "triple blocks is a design note, not implemented"}))

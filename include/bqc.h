@@ -155,6 +155,19 @@ int bqc_t_submit(bqc_server* s, int32_t nocc, int32_t nvir,
                  uint64_t* ticket);
 
 /*
+ * bqc_t_submit with a choice of input residency.  inputs_on_device = 1: the
+ * seven pointers are device pointers on the server's device (they are read
+ * in place, never copied, and must stay valid and unmodified until the
+ * ticket's terminal poll; the request's footprint is then its workspace
+ * only).  inputs_on_device = 0 is bqc_t_submit.  Thread-safe.
+ */
+int bqc_t_submit_ex(bqc_server* s, int32_t nocc, int32_t nvir,
+                    const double* eps_o, const double* eps_v,
+                    const double* t1, const double* t2,
+                    const double* ovvv, const double* ooov, const double* ovov,
+                    int32_t inputs_on_device, uint64_t* ticket);
+
+/*
  * Non-blocking status of a ticket: BQC_PENDING while queued or running;
  * BQC_OK with *E_T (and *stats if non-NULL) written once it finished; a
  * negative code if the request failed.  A terminal return consumes the

@@ -99,6 +99,9 @@ def lib():
                 L.bqc_t_submit.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, *seven,
                                            ctypes.POINTER(ctypes.c_uint64)]
                 L.bqc_t_submit.restype = ctypes.c_int
+                L.bqc_t_submit_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, *seven,
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+                L.bqc_t_submit_ex.restype = ctypes.c_int
                 L.bqc_t_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _dp, ctypes.POINTER(TStats)]
                 L.bqc_t_poll.restype = ctypes.c_int
                 L.bqc_t_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _dp, ctypes.POINTER(TStats)]
@@ -214,11 +217,14 @@ class Server:
         self._keep = {}
 
     def submit(self, nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov) -> int:
+        """Host numpy arrays (uploaded at admission) or device torch tensors
+        (read in place; keep them unmodified until the ticket finishes)."""
         ptrs, on_dev, keep = _ptrs((eps_o, eps_v, t1, t2, ovvv, ooov, ovov))
-        if on_dev:
-            raise ValueError("bqc_t_submit takes host arrays")
         t = ctypes.c_uint64()
-        _check(lib().bqc_t_submit(self._h, nocc, nvir, *ptrs, ctypes.byref(t)))
+        if on_dev:
+            import torch
+            torch.cuda.current_stream(eps_o.device).synchronize()  # inputs complete before the server reads them
+        _check(lib().bqc_t_submit_ex(self._h, nocc, nvir, *ptrs, 1 if on_dev else 0, ctypes.byref(t)))
         self._keep[t.value] = keep
         return t.value
 

@@ -49,6 +49,7 @@ int validate(int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;  // epilogue stream of the two-stream pipeline
     void* ws = nullptr;
     size_t ws_size = 0;
     void* in = nullptr;
@@ -115,6 +116,7 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     Ctx* ctx = acquire_ctx(op.device);
     struct Rel { Ctx* c; ~Rel() { release_ctx(c); } } rel{ctx};
     if (!ctx->stream) BQC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    if (!ctx->side) BQC_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     if (!ctx->host_energy) BQC_HIP(hipHostMalloc((void**)&ctx->host_energy, 256, hipHostMallocDefault));
     hipStream_t st = op.stream ? (hipStream_t)op.stream : ctx->stream;
 
@@ -159,7 +161,7 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     const Plan plan = make_plan(o, v, op.precision);
     ensure(ctx->ws, ctx->ws_size, (size_t)workspace_bytes(o, v, op.precision));
     SolveStats ss;
-    enqueue_solve(plan, in, ctx->ws, nullptr, st, op.timing != 0, stats ? &ss : nullptr);
+    enqueue_solve(plan, in, ctx->ws, nullptr, st, ctx->side, op.timing != 0, stats ? &ss : nullptr);
     BQC_HIP(hipMemcpyAsync(ctx->host_energy, workspace_energy(ctx->ws, o, v, op.precision), sizeof(double),
                            hipMemcpyDeviceToHost, st));
     std::vector<double> etrip;

@@ -54,25 +54,32 @@ struct DevInputs {
     const double* ovov = nullptr;
 };
 
-// Contraction operands in the contraction precision (a1):
-//   ovvv_c [o][v][v][v]  = (ia|bc)
-//   t2_c   [o][o][v][v]  = t_ij^ab
-//   t2l_c  [o][v][v][o]  t2l[P][y][u][l] = t_lP^yu
-//   hoo_c  [o][o][v][o]  hoo[q][P][u][l] = -(Pu|ql) = -ooov[q][l][P][u]
-// For BF16X3 each array holds the hi part followed by the lo part.
-// For FP8 each array holds e4m3 bytes; the scales sit in separate arrays
-// with one power-of-two exponent per 32 consecutive contraction elements.
+// Contraction operands in the contraction precision (a1), chunk-major: a
+// factor is a set of matrices M of v rows; for each 128-byte chunk of the
+// contraction index (KC elements: 16 FP64, 32 FP32, 32 bf16 hi + 32 lo for
+// BF16X3) all v rows are contiguous:  byte offset of (M, row r, chunk c) =
+// ((M * nchunk + c) * v + r) * 128.  Contraction lengths are zero-padded to
+// Kv = roundup(v, KPAD) and Ko = roundup(o, KPAD).
+//   ovvv  M = P*v + y, r = u, k = d:  (Pu|yd)
+//   t2    M = P*o + q, r = u, k = d:  t_Pq^ud
+//   t2l   M = P*v + y, r = u, k = l:  t_lP^yu
+//   hoo   M = q*o + P, r = u, k = l:  -(Pu|ql)
+// FP8: KC = 128 e4m3 bytes per chunk and contraction lengths padded to 128;
+// each row of each chunk also has a 4-byte word of E8M0 exponents, one per
+// 32 elements (scale 2^(byte - 127)), at ((M * nchunk + c) * v + r) * 4.
+constexpr int KPAD = 32;
+int chunk_elems(int precision);
+int kpad_of(int precision);
 struct Operands {
     const void* ovvv = nullptr;
     const void* t2 = nullptr;
     const void* t2l = nullptr;
     const void* hoo = nullptr;
-    // FP8 only: E8M0 exponents per 32-element block along the contraction
-    const uint8_t* ovvv_s = nullptr;
-    const uint8_t* t2_s = nullptr;
-    const uint8_t* t2l_s = nullptr;
-    const uint8_t* hoo_s = nullptr;
-    int64_t lo_off_ovvv = 0, lo_off_t2 = 0, lo_off_t2l = 0, lo_off_hoo = 0;  // BF16X3 lo offsets (elements)
+    const uint32_t* ovvv_s = nullptr;  // FP8 scale words
+    const uint32_t* t2_s = nullptr;
+    const uint32_t* t2l_s = nullptr;
+    const uint32_t* hoo_s = nullptr;
+    int Kv = 0, Ko = 0;
 };
 
 // One launch of the contraction kernel covers a batch of triples.
@@ -97,6 +104,13 @@ struct EpiLaunch {
     int norbit;
     double* partial;       // [ntrip][norbit]
 };
+
+// Padded contraction lengths and matrix counts of the four factors.
+struct Sizes {
+    int Kv, Ko;
+    int64_t m_ovvv, m_t2, m_t2l, m_hoo;  // matrices per factor
+};
+Sizes factor_sizes(int o, int v, int precision);
 
 // ------------------------------------------------------------------ launchers
 void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* ops,
@@ -134,9 +148,12 @@ Plan make_plan(int o, int v, int precision);
 
 // A solve whose inputs are resident on the device.  The caller owns `ws`
 // (workspace_bytes(o, v, precision) bytes, 256-byte aligned) and the stream.
-// Enqueues everything; the energy lands in *d_energy (device) and the
-// per-triple energies in d_etrip (device, num_triples(o) doubles).
+// Enqueues everything; the energy and the per-triple energies stay in the
+// workspace (workspace_energy / workspace_etrip).
+// `side` is a second stream of the same device on which the epilogues run,
+// overlapping the contractions on `st`; everything is ordered back onto `st`.
+// Returns after `st` has drained (the solve is complete).
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
-                   hipStream_t st, bool timing, SolveStats* stats);
+                   hipStream_t st, hipStream_t side, bool timing, SolveStats* stats);
 
 }  // namespace bqc

@@ -1,185 +1,363 @@
-// Contraction kernels of the (T) energy (paper section 2.4.2, Eq. 2) for the
-// FP64 and FP32 modes: MFMA 16x16x4 GEMMs on LDS-staged tiles.
+// Contraction kernels of the (T) energy (paper section 2.4.2, Eq. 2):
+// MFMA GEMMs on LDS-staged tiles in FP64, FP32, split-BF16x3 and FP8.
 //
-// For an occupied triple (i, j, k) the six permuted terms of W are paired by
-// the virtual index that neither factor of the particle product carries
-// along a row of its GEMM.  With q the occupied index whose virtual y is held
-// fixed and (P, u), (R, w) the other two pairs, each pair of terms is
+// For an occupied triple (i, j, k) the six permuted terms of W are paired so
+// that both members of a pair hold the same virtual index y fixed.  With q
+// the occupied index carrying y and (P, u), (R, w) the other two pairs,
 //
 //   H[y][u][w] = X_{PqR}(u, y, w) + X_{RqP}(w, y, u)
-//              = sum_K Row[y][u][K] * Col[y][w][K],   K over 4 segments:
+//              = sum_K Row[y][u][K] * Col[y][w][K],   K over four segments:
 //     seg 0 (v): Row = (Pu|yd)          Col = t_{Rq}^{wd}
 //     seg 1 (o): Row = -(Pu|ql)         Col = t_{lR}^{yw}
 //     seg 2 (v): Row = t_{Pq}^{ud}      Col = (Rw|yd)
 //     seg 3 (o): Row = t_{lP}^{yu}      Col = -(Rw|ql)
-// (X_pqr(x,y,z) = sum_d (px|yd) t_rq^zd - sum_l (px|ql) t_lr^yz.)  The three
-// pairs are H_a (q=i, P=j, R=k), H_b (q=j, P=i, R=k), H_c (q=k, P=i, R=j), so
-//   W[a][b][c] = H_a[a][b][c] + H_b[b][a][c] + H_c[c][a][b].
-// In every segment exactly one factor depends on the plane index y; a work
-// group computes G_NW consecutive planes (one per wave) of a 64 x 64 (u, w)
-// tile and stages the plane-independent factor once in LDS for all waves.
+// where X_pqr(x,y,z) = sum_d (px|yd) t_rq^zd - sum_l (px|ql) t_lr^yz.  The
+// three pairs are H_a (q=i, P=j, R=k), H_b (q=j, P=i, R=k) and
+// H_c (q=k, P=i, R=j), so that W[a][b][c] = H_a[a][b][c] + H_b[b][a][c] +
+// H_c[c][a][b].  Particle and hole terms therefore run on the same MFMA
+// tiles (K = 2v + 2o per plane).
+//
+// Work decomposition: one work group = one plane y of one pair of one
+// triple, and a tile of up to 160 x 160 (u, w).  The 16-row blocks of v are
+// split evenly over the tiles (v = 300: 19 blocks -> 10 + 9), and each of the
+// four waves owns up to 5 x 5 blocks.  A wave always runs all 25 block
+// products (rows past the tile are zero in LDS and their results are not
+// stored): a branch per MFMA would cost more than the idle blocks.  Operands are staged through LDS in
+// stages of 128 bytes per row (8 16-byte vectors, swizzled so that the
+// fragment reads are free of bank conflicts), double-buffered through
+// registers.  Within a stage, MFMA lane group g (lanes 16g..16g+15) takes the
+// contraction elements [g*KC/4, (g+1)*KC/4), so each fragment is two 16-byte
+// LDS reads; A and B use the same assignment, so every element of the stage
+// is contracted exactly once.
 #include "bqc_internal.h"
 
 namespace bqc {
 namespace {
 
-constexpr int G_NW = 4;            // waves = planes per work group
-constexpr int G_BM = 64;           // u rows per wave tile
-constexpr int G_BN = 64;           // w cols per wave tile
-constexpr int G_KC = 16;           // contraction elements per LDS stage
-constexpr int G_LD = G_KC + 1;     // LDS row stride (elements), odd to spread banks
-constexpr int G_ROWS = G_BM * (1 + G_NW);  // shared rows + per-wave rows
-constexpr int G_THREADS = 64 * G_NW;
-constexpr int G_PER_THREAD = G_ROWS * G_KC / G_THREADS;
-static_assert(G_BM == G_BN, "shared and dependent tiles have the same row count");
-static_assert(G_ROWS * G_KC % G_THREADS == 0, "stage loads divide evenly");
+constexpr int TB = 10;                 // max 16-blocks per tile side
+constexpr int WB = 5;                  // max 16-blocks per wave side (2 x 2 waves)
+constexpr int TILE = TB * 16;          // 160
+constexpr int NROW = 2 * TILE;         // LDS rows: Row operand, then Col operand
+constexpr int ROWB = 128;              // bytes per LDS row and stage
+constexpr int NTHR = 256;
+constexpr int NVEC = NROW * (ROWB / 16) / NTHR;  // 16-byte vectors per thread per stage
+static_assert(NVEC * NTHR == NROW * 8, "stage loads divide evenly");
+static_assert((NTHR / 8) * (NVEC / 2) == TILE, "half of each thread's vectors are Row rows");
 
-template <typename T>
-struct Mfma;
-// Operand layout of both 16x16x4 instructions: lane l holds A[l % 16][l / 16]
-// and B[l / 16][l % 16].  The accumulator layouts differ: register r of lane l
-// holds D[row(l, r)][l % 16] with row = (l / 16) + 4 r for FP64 and
-// row = 4 (l / 16) + r for FP32.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// Mode traits.  E = element type in memory, KC = contraction elements per stage.
+template <int PREC>
+struct Mode;
 template <>
-struct Mfma<double> {
-    typedef double acc4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc4 op(double a, double b, acc4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
+struct Mode<0> {  // FP64 operands, FP64 MFMA 16x16x4
+    typedef double E;
+    typedef d4 Acc;
+    typedef double HT;
+    static constexpr int KC = 16;
     static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 template <>
-struct Mfma<float> {
-    typedef float acc4 __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc4 op(float a, float b, acc4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
+struct Mode<1> {  // FP32 operands, FP32 MFMA 16x16x4
+    typedef float E;
+    typedef f4 Acc;
+    typedef float HT;
+    static constexpr int KC = 32;
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct Mode<2> {  // bf16 hi/lo operands, bf16 MFMA 16x16x32, three products
+    typedef uint16_t E;
+    typedef f4 Acc;
+    typedef float HT;
+    static constexpr int KC = 32;
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T>
-struct Seg {
-    const T* sh;       // plane-independent factor
-    int64_t sh_row;
-    const T* dep;      // plane-dependent factor
-    int64_t dep_row, dep_plane;
-    int len;
-    bool dep_is_row;   // true: the dependent factor indexes u (rows); false: w (cols)
+template <>
+struct Mode<3> {  // FP8 e4m3 operands, E8M0 scale per 32 elements, MX-scaled MFMA 16x16x128
+    typedef uint8_t E;
+    typedef f4 Acc;
+    typedef float HT;
+    static constexpr int KC = 128;
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T>
-__device__ __forceinline__ Seg<T> make_seg(int s, int o, int v, int q, int P, int R,
-                                           const T* ovvv, const T* t2, const T* t2l,
-                                           const T* hoo) {
-    const int64_t v2 = (int64_t)v * v, v3 = v2 * v, vo = (int64_t)v * o;
-    Seg<T> g;
+typedef int i8v __attribute__((ext_vector_type(8)));
+
+// Byte offset of 16-byte vector q of LDS row r (XOR swizzle by row pair).
+__device__ __forceinline__ int lds_off(int r, int q) { return r * ROWB + ((q ^ ((r >> 1) & 7)) << 4); }
+
+// Balanced split of nblk 16-blocks into ntile tiles.
+__device__ __forceinline__ void tile_range(int t, int nblk, int ntile, int& start, int& count) {
+    const int base = nblk / ntile, extra = nblk % ntile;
+    start = t * base + min(t, extra);
+    count = base + (t < extra ? 1 : 0);
+}
+
+// Matrices and chunk counts of the two factors of segment s (see the
+// operand layout in bqc_internal.h).
+struct SegGeom {
+    int64_t row_mat, col_mat;
+    int nchunk;           // contraction chunks of the segment
+    int arr_row, arr_col; // 0 ovvv, 1 t2, 2 t2l, 3 hoo
+};
+
+__device__ __forceinline__ SegGeom seg_geom(int s, int o, int v, int nch_v, int nch_o, int q, int P, int R,
+                                            int y) {
+    SegGeom g;
     switch (s) {
-        case 0:  // Row (Pu|yd) = ovvv[P][u][y][d];  Col t_Rq^wd = t2[R][q][w][d]
-            g.dep = ovvv + P * v3; g.dep_row = v2; g.dep_plane = v; g.dep_is_row = true;
-            g.sh = t2 + ((int64_t)R * o + q) * v2; g.sh_row = v; g.len = v;
+        case 0:  // Row (Pu|yd): ovvv[P*v+y]   Col t_Rq^wd: t2[R*o+q]
+            g.row_mat = (int64_t)P * v + y; g.arr_row = 0;
+            g.col_mat = (int64_t)R * o + q; g.arr_col = 1;
+            g.nchunk = nch_v;
             break;
-        case 1:  // Row -(Pu|ql) = hoo[q][P][u][l];  Col t_lR^yw = t2l[R][y][w][l]
-            g.sh = hoo + ((int64_t)q * o + P) * vo; g.sh_row = o;
-            g.dep = t2l + R * v2 * o; g.dep_row = o; g.dep_plane = vo; g.dep_is_row = false;
-            g.len = o;
+        case 1:  // Row -(Pu|ql): hoo[q*o+P]   Col t_lR^yw: t2l[R*v+y]
+            g.row_mat = (int64_t)q * o + P; g.arr_row = 3;
+            g.col_mat = (int64_t)R * v + y; g.arr_col = 2;
+            g.nchunk = nch_o;
             break;
-        case 2:  // Row t_Pq^ud = t2[P][q][u][d];  Col (Rw|yd) = ovvv[R][w][y][d]
-            g.sh = t2 + ((int64_t)P * o + q) * v2; g.sh_row = v;
-            g.dep = ovvv + R * v3; g.dep_row = v2; g.dep_plane = v; g.dep_is_row = false;
-            g.len = v;
+        case 2:  // Row t_Pq^ud: t2[P*o+q]     Col (Rw|yd): ovvv[R*v+y]
+            g.row_mat = (int64_t)P * o + q; g.arr_row = 1;
+            g.col_mat = (int64_t)R * v + y; g.arr_col = 0;
+            g.nchunk = nch_v;
             break;
-        default:  // Row t_lP^yu = t2l[P][y][u][l];  Col -(Rw|ql) = hoo[q][R][w][l]
-            g.dep = t2l + P * v2 * o; g.dep_row = o; g.dep_plane = vo; g.dep_is_row = true;
-            g.sh = hoo + ((int64_t)q * o + R) * vo; g.sh_row = o;
-            g.len = o;
+        default:  // Row t_lP^yu: t2l[P*v+y]   Col -(Rw|ql): hoo[q*o+R]
+            g.row_mat = (int64_t)P * v + y; g.arr_row = 2;
+            g.col_mat = (int64_t)q * o + R; g.arr_col = 3;
+            g.nchunk = nch_o;
             break;
     }
     return g;
 }
 
-// Occupied roles of pair h for triple (i, j, k): (q, P, R).
+__device__ __forceinline__ const char* arr_base(const Operands& ops, int a) {
+    const void* p = a == 0 ? ops.ovvv : a == 1 ? ops.t2 : a == 2 ? ops.t2l : ops.hoo;
+    return (const char*)p;
+}
+__device__ __forceinline__ const uint32_t* scale_base(const Operands& ops, int a) {
+    return a == 0 ? ops.ovvv_s : a == 1 ? ops.t2_s : a == 2 ? ops.t2l_s : ops.hoo_s;
+}
+
 __device__ __forceinline__ void roles(int h, int i, int j, int k, int& q, int& P, int& R) {
     if (h == 0) { q = i; P = j; R = k; }
     else if (h == 1) { q = j; P = i; R = k; }
     else { q = k; P = i; R = j; }
 }
 
-template <typename T, typename HT>
-__global__ __launch_bounds__(G_THREADS) void h_gemm_kernel(GemmLaunch g, int n_tiles,
-                                                             int n_ut, int n_yg, int per_xcd) {
-    // XCD-aware order: hardware block n runs on XCD n % 8; give each XCD a
-    // contiguous range of logical tiles so tiles sharing a factor share an L2.
+template <int PREC>
+__global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile,
+                                                           int per_xcd) {
+    typedef Mode<PREC> M;
+    typedef typename M::E E;
+    typedef typename M::Acc Acc;
+    typedef typename M::HT HT;
+    constexpr int KC = M::KC;
+
+    // XCD-aware order: hardware block n runs on XCD n % 8; each XCD gets a
+    // contiguous range of logical tiles (neighbours share operands in L2).
     const int n = blockIdx.x;
     const int L = (n % 8) * per_xcd + n / 8;
-    if (L >= n_tiles) return;
-    const int o = g.o, v = g.v;
+    if (L >= n_wg) return;
+    const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
     int rem = L;
-    const int wt = rem % n_ut; rem /= n_ut;
-    const int ut = rem % n_ut; rem /= n_ut;
-    const int yg = rem % n_yg; rem /= n_yg;
+    const int tw = rem % ntile; rem /= ntile;
+    const int tu = rem % ntile; rem /= ntile;
+    const int y = rem % v; rem /= v;
     const int h = rem % 3;
     const int t = rem / 3;
     const int4 tr = g.trip[t];
     int q, P, R;
     roles(h, tr.x, tr.y, tr.z, q, P, R);
 
-    const T* ovvv = (const T*)g.ops.ovvv;
-    const T* t2 = (const T*)g.ops.t2;
-    const T* t2l = (const T*)g.ops.t2l;
-    const T* hoo = (const T*)g.ops.hoo;
+    int ub, un, wb, wn;  // tile block start / count along u and w
+    tile_range(tu, nblk, ntile, ub, un);
+    tile_range(tw, nblk, ntile, wb, wn);
 
-    const int u0 = ut * G_BM, w0 = wt * G_BN, y0 = yg * G_NW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wu = wave & 1, ww = wave >> 1;
+    const int uh = (un + 1) >> 1, wh = (wn + 1) >> 1;
+    const int am = wu ? un - uh : uh;       // active row blocks of this wave
+    const int an = ww ? wn - wh : wh;       // active col blocks of this wave
+    const int arow0 = (wu ? uh : 0) * 16;   // first LDS Row-operand row of this wave
+    const int brow0 = TILE + (ww ? wh : 0) * 16;
 
-    __shared__ T lds[2][G_ROWS * G_LD];
+    __shared__ __attribute__((aligned(16))) char lds[2][NROW * ROWB];
+    // FP8 only: the E8M0 exponent word (4 x 32 elements) of every staged row
+    __shared__ uint32_t lds_s[2][PREC == 3 ? NROW : 1];
 
-    typedef typename Mfma<T>::acc4 acc4;
-    acc4 acc[4][4];
+    Acc acc[WB][WB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < WB; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = acc4{0, 0, 0, 0};
+        for (int b = 0; b < WB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
-    // chunk bookkeeping: segments of length v, o, v, o in chunks of G_KC
-    const int nch_v = ceil_div(v, G_KC), nch_o = ceil_div(o, G_KC);
+    // This thread's 16-byte vector qv of each staged row, and its rows: vector
+    // e covers LDS row (tid / 8) + 32 e; rows [0, TILE) hold the Row factor
+    // (u), rows [TILE, 2 TILE) the Col factor (w).  Byte offsets within a
+    // chunk block are fixed for the work group.
+    const int qv = tid & 7;
+    int off[NVEC];
+    bool ok[NVEC];
+#pragma unroll
+    for (int e = 0; e < NVEC; ++e) {
+        const int row = (tid >> 3) + e * (NTHR / 8);
+        const int r = e < NVEC / 2 ? row : row - TILE;
+        const int gr = (e < NVEC / 2 ? ub : wb) * 16 + r;
+        ok[e] = r < (e < NVEC / 2 ? un : wn) * 16 && gr < v;
+        off[e] = gr * ROWB + qv * 16;
+    }
+
+    const int nch_v = Kv / KC, nch_o = Ko / KC;
     const int nch = 2 * nch_v + 2 * nch_o;
-    auto chunk_seg = [&](int c, int& s, int& k0) {
-        if (c < nch_v) { s = 0; k0 = c * G_KC; }
-        else if (c < nch_v + nch_o) { s = 1; k0 = (c - nch_v) * G_KC; }
-        else if (c < 2 * nch_v + nch_o) { s = 2; k0 = (c - nch_v - nch_o) * G_KC; }
-        else { s = 3; k0 = (c - 2 * nch_v - nch_o) * G_KC; }
+    auto chunk_seg = [&](int c, int& s, int& kb) {
+        if (c < nch_v) { s = 0; kb = c; }
+        else if (c < nch_v + nch_o) { s = 1; kb = c - nch_v; }
+        else if (c < 2 * nch_v + nch_o) { s = 2; kb = c - nch_v - nch_o; }
+        else { s = 3; kb = c - 2 * nch_v - nch_o; }
     };
+    const int64_t blk = (int64_t)v * ROWB;  // bytes of one chunk block (all v rows)
 
-    T reg[G_PER_THREAD];
-    auto load = [&](int c) {
-        int s, k0;
-        chunk_seg(c, s, k0);
-        const Seg<T> sg = make_seg<T>(s, o, v, q, P, R, ovvv, t2, t2l, hoo);
-        const int sh0 = sg.dep_is_row ? w0 : u0;
-        const int dp0 = sg.dep_is_row ? u0 : w0;
+    // FP8 scale words: thread tid stages rows tid and tid + 256 (< NROW)
+    constexpr int NSROW = (NROW + NTHR - 1) / NTHR;
+    int srow_g[NSROW];
+    bool srow_ok[NSROW];
+    if constexpr (PREC == 3) {
 #pragma unroll
-        for (int e = 0; e < G_PER_THREAD; ++e) {
-            const int idx = tid + e * G_THREADS;
-            const int row = idx / G_KC, kk = idx % G_KC, k = k0 + kk;
-            T val = T(0);
-            if (row < G_BM) {
-                const int gr = sh0 + row;
-                if (gr < v && k < sg.len) val = sg.sh[(int64_t)gr * sg.sh_row + k];
-            } else {
-                const int wv = (row - G_BM) / G_BM, r = (row - G_BM) % G_BM;
-                const int gr = dp0 + r, y = y0 + wv;
-                if (gr < v && y < v && k < sg.len)
-                    val = sg.dep[(int64_t)y * sg.dep_plane + (int64_t)gr * sg.dep_row + k];
+        for (int e = 0; e < NSROW; ++e) {
+            const int row = tid + e * NTHR;
+            const bool isrow = row < TILE;
+            const int r = isrow ? row : row - TILE;
+            const int gr = (isrow ? ub : wb) * 16 + r;
+            srow_ok[e] = row < NROW && r < (isrow ? un : wn) * 16 && gr < v;
+            srow_g[e] = gr;
+        }
+    }
+
+    u4 reg[NVEC];
+    uint32_t sreg[NSROW];
+    auto load = [&](int c) {
+        int s, kb;
+        chunk_seg(c, s, kb);
+        const SegGeom sg = seg_geom(s, o, v, nch_v, nch_o, q, P, R, y);
+        const char* rb = arr_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * blk;
+        const char* cb = arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * blk;
+#pragma unroll
+        for (int e = 0; e < NVEC; ++e) {
+            const char* base = e < NVEC / 2 ? rb : cb;
+            reg[e] = ok[e] ? *(const u4*)(base + off[e]) : u4{0, 0, 0, 0};
+        }
+        if constexpr (PREC == 3) {
+            const uint32_t* rs = scale_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * (int64_t)v;
+            const uint32_t* cs = scale_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * (int64_t)v;
+#pragma unroll
+            for (int e = 0; e < NSROW; ++e) {
+                const int row = tid + e * NTHR;
+                sreg[e] = srow_ok[e] ? (row < TILE ? rs : cs)[srow_g[e]] : 0u;
             }
-            reg[e] = val;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < G_PER_THREAD; ++e) {
-            const int idx = tid + e * G_THREADS;
-            const int row = idx / G_KC, kk = idx % G_KC;
-            lds[buf][row * G_LD + kk] = reg[e];
+        for (int e = 0; e < NVEC; ++e) {
+            const int row = (tid >> 3) + e * (NTHR / 8);
+            *(u4*)(&lds[buf][lds_off(row, qv)]) = reg[e];
+        }
+        if constexpr (PREC == 3) {
+#pragma unroll
+            for (int e = 0; e < NSROW; ++e) {
+                const int row = tid + e * NTHR;
+                if (row < NROW) lds_s[buf][row] = sreg[e];
+            }
+        }
+    };
+
+    const int fr = lane & 15, fg = lane >> 4;
+    auto compute = [&](int buf) {
+        const char* L0 = lds[buf];
+        if constexpr (PREC == 3) {
+            // lane group g holds elements [32 g, 32 g + 32) of its row and the
+            // exponent byte g of the row's scale word
+            i8v af[WB], bfr[WB];
+            int sa[WB], sb[WB];
+#pragma unroll
+            for (int m = 0; m < WB; ++m) {
+                const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+                const u4 a0 = *(const u4*)(L0 + lds_off(ra, 2 * fg));
+                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 2 * fg + 1));
+                const u4 b0 = *(const u4*)(L0 + lds_off(rb, 2 * fg));
+                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 2 * fg + 1));
+                af[m] = i8v{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+                bfr[m] = i8v{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+                sa[m] = (int)((lds_s[buf][ra] >> (8 * fg)) & 0xffu);
+                sb[m] = (int)((lds_s[buf][rb] >> (8 * fg)) & 0xffu);
+            }
+#pragma unroll
+            for (int m = 0; m < WB; ++m)
+#pragma unroll
+                for (int nn = 0; nn < WB; ++nn)
+                    acc[m][nn] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[m], bfr[nn], acc[m][nn], 0, 0,
+                                                                                  0, sa[m], 0, sb[nn]);
+        } else if constexpr (PREC == 2) {
+            bf8 ah[WB], al[WB], bh[WB], bl[WB];
+#pragma unroll
+            for (int m = 0; m < WB; ++m) {
+                const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+                ah[m] = *(const bf8*)(L0 + lds_off(ra, fg));
+                al[m] = *(const bf8*)(L0 + lds_off(ra, 4 + fg));
+                bh[m] = *(const bf8*)(L0 + lds_off(rb, fg));
+                bl[m] = *(const bf8*)(L0 + lds_off(rb, 4 + fg));
+            }
+#pragma unroll
+            for (int m = 0; m < WB; ++m)
+#pragma unroll
+                for (int nn = 0; nn < WB; ++nn)
+                    acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh[nn], acc[m][nn], 0, 0, 0);
+#pragma unroll
+            for (int m = 0; m < WB; ++m)
+#pragma unroll
+                for (int nn = 0; nn < WB; ++nn)
+                    acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bl[nn], acc[m][nn], 0, 0, 0);
+#pragma unroll
+            for (int m = 0; m < WB; ++m)
+#pragma unroll
+                for (int nn = 0; nn < WB; ++nn)
+                    acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh[nn], acc[m][nn], 0, 0, 0);
+        } else {
+            constexpr int NS = (PREC == 0) ? 4 : 8;  // MFMA K-steps per stage
+            E af[WB][NS], bfr[WB][NS];
+#pragma unroll
+            for (int m = 0; m < WB; ++m) {
+                const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+                const u4 a0 = *(const u4*)(L0 + lds_off(ra, 2 * fg));
+                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 2 * fg + 1));
+                const u4 b0 = *(const u4*)(L0 + lds_off(rb, 2 * fg));
+                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 2 * fg + 1));
+                const E* pa0 = (const E*)&a0; const E* pa1 = (const E*)&a1;
+                const E* pb0 = (const E*)&b0; const E* pb1 = (const E*)&b1;
+#pragma unroll
+                for (int s = 0; s < NS / 2; ++s) {
+                    af[m][s] = pa0[s]; af[m][NS / 2 + s] = pa1[s];
+                    bfr[m][s] = pb0[s]; bfr[m][NS / 2 + s] = pb1[s];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int m = 0; m < WB; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < WB; ++nn) {
+                        if constexpr (PREC == 0)
+                            acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m][s], bfr[nn][s],
+                                                                               acc[m][nn], 0, 0, 0);
+                        else
+                            acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m][s], bfr[nn][s],
+                                                                               acc[m][nn], 0, 0, 0);
+                    }
         }
     };
 
@@ -188,63 +366,54 @@ __global__ __launch_bounds__(G_THREADS) void h_gemm_kernel(GemmLaunch g, int n_t
     __syncthreads();
     for (int c = 0; c < nch; ++c) {
         if (c + 1 < nch) load(c + 1);
-        int s, k0;
-        chunk_seg(c, s, k0);
-        const bool dep_row = (s == 0 || s == 3);
-        const T* shb = &lds[c & 1][0];
-        const T* dpb = &lds[c & 1][(G_BM + wave * G_BM) * G_LD];
-        const T* A = dep_row ? dpb : shb;
-        const T* B = dep_row ? shb : dpb;
-#pragma unroll
-        for (int ks = 0; ks < G_KC / 4; ++ks) {
-            T af[4], bf[4];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb)
-                af[mb] = A[(mb * 16 + (lane & 15)) * G_LD + ks * 4 + (lane >> 4)];
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                bf[nb] = B[(nb * 16 + (lane & 15)) * G_LD + ks * 4 + (lane >> 4)];
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < 4; ++nb) acc[mb][nb] = Mfma<T>::op(af[mb], bf[nb], acc[mb][nb]);
-        }
+        compute(c & 1);
         if (c + 1 < nch) store((c + 1) & 1);
         __syncthreads();
     }
 
-    const int y = y0 + wave;
-    if (y >= v) return;
     const int64_t v2 = (int64_t)v * v;
     HT* out = (HT*)g.hbuf + ((int64_t)(t * 3 + h) * v + y) * v2;
+    const int u00 = ub * 16 + (wu ? uh : 0) * 16, w00 = wb * 16 + (ww ? wh : 0) * 16;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int m = 0; m < WB; ++m)
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
+        for (int nn = 0; nn < WB; ++nn)
+            if (m < am && nn < an) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int u = u0 + mb * 16 + Mfma<T>::row(lane, r);
-                const int w = w0 + nb * 16 + (lane & 15);
-                if (u < v && w < v) out[(int64_t)u * v + w] = (HT)acc[mb][nb][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int u = u00 + m * 16 + M::row(lane, r);
+                    const int w = w00 + nn * 16 + fr;
+                    if (u < v && w < v) out[(int64_t)u * v + w] = (HT)acc[m][nn][r];
+                }
             }
 }
 
 }  // namespace
 
 void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st) {
-    const int n_ut = ceil_div(g.v, G_BM);
-    const int n_yg = ceil_div(g.v, G_NW);
-    const int64_t n_tiles64 = (int64_t)g.ntrip * 3 * n_yg * n_ut * n_ut;
-    if (n_tiles64 > (int64_t)1 << 30) throw Error(-1, "contraction grid too large");
-    const int n_tiles = (int)n_tiles64;
-    const int per_xcd = ceil_div(n_tiles, 8);
-    dim3 grid(per_xcd * 8), block(G_THREADS);
-    if (precision == 0)
-        hipLaunchKernelGGL((h_gemm_kernel<double, double>), grid, block, 0, st, g, n_tiles, n_ut,
-                           n_yg, per_xcd);
-    else
-        hipLaunchKernelGGL((h_gemm_kernel<float, float>), grid, block, 0, st, g, n_tiles, n_ut,
-                           n_yg, per_xcd);
+    const int nblk = ceil_div(g.v, 16);
+    const int ntile = ceil_div(nblk, TB);
+    const int64_t n64 = (int64_t)g.ntrip * 3 * g.v * ntile * ntile;
+    if (n64 > ((int64_t)1 << 31) - 8) throw Error(-1, "contraction grid too large");
+    const int n_wg = (int)n64;
+    const int per_xcd = ceil_div(n_wg, 8);
+    dim3 grid(per_xcd * 8), block(NTHR);
+    switch (precision) {
+        case 0:
+            hipLaunchKernelGGL(h_gemm_kernel<0>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
+            break;
+        case 1:
+            hipLaunchKernelGGL(h_gemm_kernel<1>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
+            break;
+        case 2:
+            hipLaunchKernelGGL(h_gemm_kernel<2>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
+            break;
+        case 3:
+            hipLaunchKernelGGL(h_gemm_kernel<3>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
+            break;
+        default:
+            throw Error(-1, "unsupported precision for the MFMA contraction");
+    }
     BQC_HIP(hipGetLastError());
 }
 

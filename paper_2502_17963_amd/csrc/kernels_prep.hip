@@ -1,11 +1,22 @@
 // Device residency and precision conversion of the (T) inputs.
 //
-// The contraction kernels read every factor as rows that are contiguous along
-// the contraction index.  (ia|bc) and t_ij^ab already are; the hole factors
-// are re-laid out once per solve:
-//   t2l[P][y][u][l] = t_lP^yu = t2[l][P][y][u]
-//   hoo[q][P][u][l] = -(Pu|ql) = -ooov[q][l][P][u]
-// and every factor is converted to the contraction precision.
+// The contraction kernels stage every factor through LDS as row tiles of one
+// 128-byte contraction chunk per row.  Each factor is therefore converted
+// once per solve into a chunk-major layout: it is a set of matrices (M) of
+// v rows (r), and for every 128-byte chunk (c) of the contraction index all
+// rows are contiguous,
+//     element (M, r, k) at  ((M * nchunk + k / KC) * v + r) * KC + k % KC,
+// so that the operand tile of one stage (up to 160 consecutive rows) is one
+// contiguous block.  The contraction index is zero-padded to Kv = roundup(v,
+// KPAD) or Ko = roundup(o, KPAD).  The factors (matrix index -> rows, k):
+//   ovvv_c  M = P*v + y:  r = u, k = d   (Pu|yd)
+//   t2_c    M = P*o + q:  r = u, k = d   t_Pq^ud
+//   t2l_c   M = P*v + y:  r = u, k = l   t_lP^yu = t2[l][P][y][u]
+//   hoo_c   M = q*o + P:  r = u, k = l   -(Pu|ql) = -ooov[q][l][P][u]
+// KC = elements per 128-byte chunk: 16 (FP64), 32 (FP32), and for the
+// split-BF16x3 mode a chunk holds 32 bf16 hi parts followed by their 32 lo
+// parts (x_hi = bf16(x), x_lo = bf16(x - x_hi)).  The FP8 mode pads to 128
+// and stores 128 e4m3 bytes per chunk row plus one E8M0 exponent per 32.
 #include "bqc_internal.h"
 
 namespace bqc {
@@ -20,6 +31,8 @@ int operand_bytes(int precision) {
     }
 }
 int hbuf_bytes(int precision) { return precision == 0 ? 8 : 4; }
+int chunk_elems(int precision) { return 128 / operand_bytes(precision); }
+int kpad_of(int precision) { return precision == 3 ? 128 : KPAD; }
 
 namespace {
 
@@ -31,93 +44,223 @@ inline dim3 grid_for(int64_t n) {
     return dim3((unsigned)(b < 1 ? 1 : b));
 }
 
-// t2l[P][y][u][l] = s * t2[l][P][y][u]; output index runs l fastest.
-template <typename T>
-__global__ void make_t2l(const double* __restrict__ t2, T* __restrict__ out, int o, int v) {
-    const int64_t n = (int64_t)o * o * v * v;
-    const int64_t v2 = (int64_t)v * v;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int l = (int)(idx % o);
-        const int64_t pyu = idx / o;  // (P, y, u) flattened: P * v^2 + y * v + u
-        out[idx] = (T)t2[(int64_t)l * o * v2 + pyu];
-    }
-}
-
-// hoo[q][P][u][l] = -ooov[q][l][P][u]
-template <typename T>
-__global__ void make_hoo(const double* __restrict__ ooov, T* __restrict__ out, int o, int v) {
-    const int64_t n = (int64_t)o * o * v * o;
-    const int64_t ov = (int64_t)o * v;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int l = (int)(idx % o);
-        const int64_t rest = idx / o;       // (q, P, u)
-        const int64_t pu = rest % ov;       // P * v + u
-        const int64_t q = rest / ov;
-        out[idx] = (T)(-ooov[(q * o + l) * ov + pu]);
-    }
-}
-
-template <typename T>
-__global__ void convert(const double* __restrict__ in, T* __restrict__ out, int64_t n) {
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-         idx += (int64_t)gridDim.x * blockDim.x)
-        out[idx] = (T)in[idx];
-}
-
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Round-to-nearest-even FP32 -> bf16 bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Source value of factor F at (matrix M, row r, contraction index k < len).
+enum Factor { F_OVVV = 0, F_T2 = 1, F_T2L = 2, F_HOO = 3 };
+
+template <int F>
+__device__ __forceinline__ double source(const double* __restrict__ src, int64_t M, int64_t r, int64_t k,
+                                         int64_t o, int64_t v) {
+    if constexpr (F == F_OVVV) {  // ovvv[P][u][y][d]
+        const int64_t P = M / v, y = M % v;
+        return src[((P * v + r) * v + y) * v + k];
+    } else if constexpr (F == F_T2) {  // t2[P][q][u][d]
+        return src[(M * v + r) * v + k];
+    } else if constexpr (F == F_T2L) {  // t2[l][P][y][u]
+        return src[k * o * v * v + M * v + r];
+    } else {  // -ooov[q][l][P][u]
+        const int64_t q = M / o, P = M % o;
+        return -src[((q * o + k) * o + P) * v + r];
+    }
+}
+
+// One thread per destination element (chunk-major order).
+template <int PREC, int F>
+__global__ void make_factor(const double* __restrict__ src, void* dst, int64_t nmat, int len, int kpad,
+                            int o, int v) {
+    constexpr int KC = (PREC == 0) ? 16 : 32;
+    const int nchunk = kpad / KC;
+    const int64_t n = nmat * nchunk * (int64_t)v * KC;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int kk = (int)(idx % KC);
+        int64_t rest = idx / KC;
+        const int64_t r = rest % v; rest /= v;
+        const int c = (int)(rest % nchunk);
+        const int64_t M = rest / nchunk;
+        const int k = c * KC + kk;
+        const double x = k < len ? source<F>(src, M, r, k, o, v) : 0.0;
+        if constexpr (PREC == 0) {
+            ((double*)dst)[idx] = x;
+        } else if constexpr (PREC == 1) {
+            ((float*)dst)[idx] = (float)x;
+        } else {
+            // chunk of 32 elements -> 32 hi parts then 32 lo parts
+            uint16_t* d = (uint16_t*)dst + (idx - kk) * 2;
+            const uint16_t h = bf16_bits((float)x);
+            d[kk] = h;
+            d[32 + kk] = bf16_bits((float)(x - (double)bf16_value(h)));
+        }
+    }
+}
+
+// OCP FP8 e4m3 (bias 7, max 448, no infinities) of y with round-to-nearest-
+// even and saturation at 448.
+__device__ __forceinline__ uint8_t e4m3_rne(double y) {
+    const uint8_t sign = y < 0.0 ? 0x80 : 0;
+    const double a = fabs(y);
+    if (!(a < 464.0)) return sign | 0x7E;               // rounds above 448 (or NaN)
+    if (a < 0.015625) {                                  // below 2^-6: subnormal, step 2^-9
+        const int m = (int)rint(a * 512.0);              // 0..8 (8 is the smallest normal)
+        return sign | (uint8_t)m;
+    }
+    int ex;
+    const double f = frexp(a, &ex);                      // a = f 2^ex, f in [0.5, 1)
+    int E = ex - 1;
+    int m = (int)rint((2.0 * f - 1.0) * 8.0);            // 3-bit mantissa, may carry
+    if (m == 8) { m = 0; E += 1; }
+    if (E > 8 || (E == 8 && m == 7)) return sign | 0x7E;
+    return sign | (uint8_t)(((E + 7) << 3) | m);
+}
+
+// FP8 factor: one thread per 32-element block of a (matrix, row, chunk):
+// exponent e = ceil(log2(amax / 448)) (so every |x| 2^-e <= 448), stored as
+// the E8M0 byte e + 127, and the 32 elements as e4m3(x 2^-e).
+template <int F>
+__global__ void make_factor_fp8(const double* __restrict__ src, uint8_t* dst, uint8_t* scl, int64_t nmat,
+                                int len, int kpad, int o, int v) {
+    const int nchunk = kpad / 128;
+    const int64_t n = nmat * nchunk * (int64_t)v * 4;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx % 4);
+        int64_t rest = idx / 4;
+        const int64_t r = rest % v; rest /= v;
+        const int c = (int)(rest % nchunk);
+        const int64_t M = rest / nchunk;
+        const int k0 = c * 128 + 32 * j;
+        double amax = 0.0;
+        for (int i = 0; i < 32; ++i)
+            if (k0 + i < len) amax = fmax(amax, fabs(source<F>(src, M, r, k0 + i, o, v)));
+        int e = -127;
+        if (amax > 0.0) {
+            int ex;
+            const double fr = frexp(amax / 448.0, &ex);
+            e = (fr == 0.5) ? ex - 1 : ex;
+            e = e < -127 ? -127 : (e > 127 ? 127 : e);
+        }
+        const int64_t row = (M * nchunk + c) * (int64_t)v + r;
+        scl[row * 4 + j] = (uint8_t)(e + 127);
+        uint8_t* d = dst + row * 128 + 32 * j;
+        for (int i = 0; i < 32; ++i) {
+            const double x = k0 + i < len ? source<F>(src, M, r, k0 + i, o, v) : 0.0;
+            d[i] = e4m3_rne(ldexp(x, -e));
+        }
+    }
+}
+
+template <int F>
+void launch_factor_fp8(const double* src, void* dst, void* scl, int64_t nmat, int len, int kpad, int o,
+                       int v, hipStream_t st) {
+    const int64_t n = nmat * (int64_t)v * (kpad / 32);
+    hipLaunchKernelGGL((make_factor_fp8<F>), grid_for(n), dim3(P_THREADS), 0, st, src, (uint8_t*)dst,
+                       (uint8_t*)scl, nmat, len, kpad, o, v);
+}
+
+void prepare_fp8(const DevInputs& in, void* ws, Operands* ops, hipStream_t st);
+
+}  // namespace
+
+Sizes factor_sizes(int o, int v, int precision) {
+    const int kp = kpad_of(precision);
+    Sizes s;
+    s.Kv = ceil_div(v, kp) * kp;
+    s.Ko = ceil_div(o, kp) * kp;
+    s.m_ovvv = (int64_t)o * v;
+    s.m_t2 = (int64_t)o * o;
+    s.m_t2l = (int64_t)o * v;
+    s.m_hoo = (int64_t)o * o;
+    return s;
+}
+
+namespace {
+
+template <int PREC, int F>
+void launch_factor(const double* src, void* dst, int64_t nmat, int len, int kpad, int o, int v,
+                   hipStream_t st) {
+    const int64_t n = nmat * (int64_t)v * kpad;
+    hipLaunchKernelGGL((make_factor<PREC, F>), grid_for(n), dim3(P_THREADS), 0, st, src, dst, nmat, len, kpad,
+                       o, v);
+}
+
+template <int PREC>
+void prepare_t(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
+    const int o = in.o, v = in.v;
+    const Sizes z = factor_sizes(o, v, PREC);
+    const int eb = operand_bytes(PREC);
+    char* p = (char*)ws;
+    void* d_ovvv = p; p += align256((size_t)z.m_ovvv * v * z.Kv * eb);
+    void* d_t2 = p;   p += align256((size_t)z.m_t2 * v * z.Kv * eb);
+    void* d_t2l = p;  p += align256((size_t)z.m_t2l * v * z.Ko * eb);
+    void* d_hoo = p;
+    launch_factor<PREC, F_OVVV>(in.ovvv, d_ovvv, z.m_ovvv, v, z.Kv, o, v, st);
+    launch_factor<PREC, F_T2>(in.t2, d_t2, z.m_t2, v, z.Kv, o, v, st);
+    launch_factor<PREC, F_T2L>(in.t2, d_t2l, z.m_t2l, o, z.Ko, o, v, st);
+    launch_factor<PREC, F_HOO>(in.ooov, d_hoo, z.m_hoo, o, z.Ko, o, v, st);
+    BQC_HIP(hipGetLastError());
+    ops->ovvv = d_ovvv;
+    ops->t2 = d_t2;
+    ops->t2l = d_t2l;
+    ops->hoo = d_hoo;
+    ops->Kv = z.Kv;
+    ops->Ko = z.Ko;
+}
+
+void prepare_fp8(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
+    const int o = in.o, v = in.v;
+    const Sizes z = factor_sizes(o, v, 3);
+    char* p = (char*)ws;
+    void* d_ovvv = p; p += align256((size_t)z.m_ovvv * v * z.Kv);
+    void* d_t2 = p;   p += align256((size_t)z.m_t2 * v * z.Kv);
+    void* d_t2l = p;  p += align256((size_t)z.m_t2l * v * z.Ko);
+    void* d_hoo = p;  p += align256((size_t)z.m_hoo * v * z.Ko);
+    void* s_ovvv = p; p += align256((size_t)z.m_ovvv * v * z.Kv / 32);
+    void* s_t2 = p;   p += align256((size_t)z.m_t2 * v * z.Kv / 32);
+    void* s_t2l = p;  p += align256((size_t)z.m_t2l * v * z.Ko / 32);
+    void* s_hoo = p;
+    launch_factor_fp8<F_OVVV>(in.ovvv, d_ovvv, s_ovvv, z.m_ovvv, v, z.Kv, o, v, st);
+    launch_factor_fp8<F_T2>(in.t2, d_t2, s_t2, z.m_t2, v, z.Kv, o, v, st);
+    launch_factor_fp8<F_T2L>(in.t2, d_t2l, s_t2l, z.m_t2l, o, z.Ko, o, v, st);
+    launch_factor_fp8<F_HOO>(in.ooov, d_hoo, s_hoo, z.m_hoo, o, z.Ko, o, v, st);
+    BQC_HIP(hipGetLastError());
+    ops->ovvv = d_ovvv; ops->t2 = d_t2; ops->t2l = d_t2l; ops->hoo = d_hoo;
+    ops->ovvv_s = (const uint32_t*)s_ovvv; ops->t2_s = (const uint32_t*)s_t2;
+    ops->t2l_s = (const uint32_t*)s_t2l; ops->hoo_s = (const uint32_t*)s_hoo;
+    ops->Kv = z.Kv;
+    ops->Ko = z.Ko;
+}
 
 }  // namespace
 
 int64_t prepare_bytes(int precision, int o, int v) {
-    const int64_t n_ovvv = (int64_t)o * v * v * v, n_t2 = (int64_t)o * o * v * v;
-    const int64_t n_t2l = n_t2, n_hoo = (int64_t)o * o * v * o;
+    const Sizes z = factor_sizes(o, v, precision);
     const int eb = operand_bytes(precision);
-    int64_t b = 0;
-    if (precision != 0) b += align256(n_ovvv * eb) + align256(n_t2 * eb);
-    b += align256(n_t2l * eb) + align256(n_hoo * eb);
-    if (precision == 3) {  // one scale byte per 32 contraction elements (rows padded)
-        b += align256(n_ovvv / v * ceil_div(v, 32)) + align256(n_t2 / v * ceil_div(v, 32));
-        b += align256(n_t2l / o * ceil_div(o, 32)) + align256(n_hoo / o * ceil_div(o, 32));
+    int64_t b = align256((size_t)z.m_ovvv * v * z.Kv * eb) + align256((size_t)z.m_t2 * v * z.Kv * eb) +
+                align256((size_t)z.m_t2l * v * z.Ko * eb) + align256((size_t)z.m_hoo * v * z.Ko * eb);
+    if (precision == 3) {  // one scale byte per 32 contraction elements
+        b += align256((size_t)z.m_ovvv * v * z.Kv / 32) + align256((size_t)z.m_t2 * v * z.Kv / 32) +
+             align256((size_t)z.m_t2l * v * z.Ko / 32) + align256((size_t)z.m_hoo * v * z.Ko / 32);
     }
     return b;
 }
 
-void launch_prepare_lowp(int precision, const DevInputs& in, void* ws, Operands* ops,
-                         hipStream_t st);
-
 void launch_prepare(int precision, const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
-    const int o = in.o, v = in.v;
-    const int64_t n_ovvv = (int64_t)o * v * v * v, n_t2 = (int64_t)o * o * v * v;
-    const int64_t n_hoo = (int64_t)o * o * v * o;
-    char* p = (char*)ws;
-    if (precision == 0) {
-        ops->ovvv = in.ovvv;
-        ops->t2 = in.t2;
-        double* t2l = (double*)p; p += align256(n_t2 * 8);
-        double* hoo = (double*)p;
-        hipLaunchKernelGGL(make_t2l<double>, grid_for(n_t2), dim3(P_THREADS), 0, st, in.t2, t2l, o, v);
-        hipLaunchKernelGGL(make_hoo<double>, grid_for(n_hoo), dim3(P_THREADS), 0, st, in.ooov, hoo, o, v);
-        ops->t2l = t2l;
-        ops->hoo = hoo;
-    } else if (precision == 1) {
-        float* ovvv = (float*)p; p += align256(n_ovvv * 4);
-        float* t2 = (float*)p; p += align256(n_t2 * 4);
-        float* t2l = (float*)p; p += align256(n_t2 * 4);
-        float* hoo = (float*)p;
-        hipLaunchKernelGGL(convert<float>, grid_for(n_ovvv), dim3(P_THREADS), 0, st, in.ovvv, ovvv, n_ovvv);
-        hipLaunchKernelGGL(convert<float>, grid_for(n_t2), dim3(P_THREADS), 0, st, in.t2, t2, n_t2);
-        hipLaunchKernelGGL(make_t2l<float>, grid_for(n_t2), dim3(P_THREADS), 0, st, in.t2, t2l, o, v);
-        hipLaunchKernelGGL(make_hoo<float>, grid_for(n_hoo), dim3(P_THREADS), 0, st, in.ooov, hoo, o, v);
-        ops->ovvv = ovvv;
-        ops->t2 = t2;
-        ops->t2l = t2l;
-        ops->hoo = hoo;
-    } else {
-        launch_prepare_lowp(precision, in, ws, ops, st);
+    switch (precision) {
+        case 0: prepare_t<0>(in, ws, ops, st); break;
+        case 1: prepare_t<1>(in, ws, ops, st); break;
+        case 2: prepare_t<2>(in, ws, ops, st); break;
+        case 3: prepare_fp8(in, ws, ops, st); break;
+        default: throw Error(-1, "unknown precision");
     }
-    BQC_HIP(hipGetLastError());
 }
 
 }  // namespace bqc

@@ -24,6 +24,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/bqc.h"
 #include "bqc_internal.h"
@@ -94,6 +95,7 @@ struct Request {
     clk::time_point t_submit, t_admit;
     size_t bytes = 0, off = 0;
     int bypassed = 0;
+    bool dev_in = false;  // inputs are device pointers read in place
 };
 
 }  // namespace
@@ -110,6 +112,7 @@ struct bqc_server {
     std::unordered_map<uint64_t, bqc::Request*> reqs;
     std::vector<std::thread> slots;
     std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> sides;  // epilogue stream of each slot
     std::vector<double*> pinned;
     bool stop = false;
     uint64_t next_ticket = 1;
@@ -118,34 +121,40 @@ struct bqc_server {
 namespace bqc {
 namespace {
 
-size_t request_bytes(int o, int v, int precision) {
-    return a256((size_t)input_bytes(o, v)) + a256((size_t)workspace_bytes(o, v, precision));
+size_t request_bytes(int o, int v, int precision, bool dev_in) {
+    return (dev_in ? 0 : a256((size_t)input_bytes(o, v))) + a256((size_t)workspace_bytes(o, v, precision));
 }
 
 // Runs one admitted request on the slot's stream; returns the BQC code.
-int run_request(bqc_server* s, Request* r, hipStream_t st, double* pinned) {
+int run_request(bqc_server* s, Request* r, hipStream_t st, hipStream_t side, double* pinned) {
     const int o = r->o, v = r->v;
     char* base = (char*)s->arena_base + r->off;
     const size_t sizes[7] = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v,
                              (size_t)o * v * v * v, (size_t)o * o * o * v, (size_t)o * v * o * v};
     const double* dst[7];
-    char* p = base;
-    const auto u0 = clk::now();
-    for (int a = 0; a < 7; ++a) {
-        BQC_HIP(hipMemcpyAsync(p, r->src[a], sizes[a] * sizeof(double), hipMemcpyHostToDevice, st));
-        dst[a] = (const double*)p;
-        p += a256(sizes[a] * sizeof(double));
+    double upload_s = 0.0;
+    void* ws = base;
+    if (r->dev_in) {
+        for (int a = 0; a < 7; ++a) dst[a] = r->src[a];
+    } else {
+        char* p = base;
+        const auto u0 = clk::now();
+        for (int a = 0; a < 7; ++a) {
+            BQC_HIP(hipMemcpyAsync(p, r->src[a], sizes[a] * sizeof(double), hipMemcpyHostToDevice, st));
+            dst[a] = (const double*)p;
+            p += a256(sizes[a] * sizeof(double));
+        }
+        BQC_HIP(hipStreamSynchronize(st));
+        upload_s = std::chrono::duration<double>(clk::now() - u0).count();
+        ws = base + a256((size_t)input_bytes(o, v));
     }
-    BQC_HIP(hipStreamSynchronize(st));
-    const double upload_s = std::chrono::duration<double>(clk::now() - u0).count();
-    void* ws = base + a256((size_t)input_bytes(o, v));
     DevInputs in;
     in.o = o; in.v = v;
     in.eps_o = dst[0]; in.eps_v = dst[1]; in.t1 = dst[2]; in.t2 = dst[3];
     in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
     const Plan plan = make_plan(o, v, s->precision);
     SolveStats ss;
-    enqueue_solve(plan, in, ws, nullptr, st, false, &ss);
+    enqueue_solve(plan, in, ws, nullptr, st, side, false, &ss);
     BQC_HIP(hipMemcpyAsync(pinned, workspace_energy(ws, o, v, s->precision), sizeof(double),
                            hipMemcpyDeviceToHost, st));
     BQC_HIP(hipStreamSynchronize(st));
@@ -180,6 +189,7 @@ Request* admit_locked(bqc_server* s) {
 void slot_main(bqc_server* s, int idx) {
     (void)hipSetDevice(s->device);
     hipStream_t st = s->streams[idx];
+    hipStream_t side = s->sides[idx];
     double* pinned = s->pinned[idx];
     for (;;) {
         Request* r = nullptr;
@@ -197,7 +207,7 @@ void slot_main(bqc_server* s, int idx) {
         int rc;
         std::string err;
         try {
-            rc = run_request(s, r, st, pinned);
+            rc = run_request(s, r, st, side, pinned);
         } catch (const Error& e) {
             rc = e.code;
             err = e.what();
@@ -246,6 +256,9 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
             hipStream_t st;
             BQC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
             s->streams.push_back(st);
+            hipStream_t sd;
+            BQC_HIP(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+            s->sides.push_back(sd);
             double* p = nullptr;
             BQC_HIP(hipHostMalloc((void**)&p, 256, hipHostMallocDefault));
             s->pinned.push_back(p);
@@ -253,6 +266,7 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
     } catch (...) {
         (void)hipSetDevice(prev);
         for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        for (hipStream_t st : s->sides) (void)hipStreamDestroy(st);
         for (double* p : s->pinned) (void)hipHostFree(p);
         if (s->arena_base) (void)hipFree(s->arena_base);
         delete s->arena;
@@ -283,6 +297,7 @@ int destroy_impl(bqc_server* s) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    for (hipStream_t st : s->sides) (void)hipStreamDestroy(st);
     for (double* p : s->pinned) (void)hipHostFree(p);
     (void)hipFree(s->arena_base);
     (void)hipSetDevice(prev);
@@ -292,17 +307,31 @@ int destroy_impl(bqc_server* s) {
     return BQC_OK;
 }
 
-int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7], uint64_t* ticket) {
+int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7], bool dev_in,
+                uint64_t* ticket) {
     if (!s || !ticket) return fail(BQC_EINVAL, "null argument");
-    int rc = validate(o, v, src[0], src[1], src[2], src[3], src[4], src[5], src[6], true);
+    int rc = validate(o, v, src[0], src[1], src[2], src[3], src[4], src[5], src[6], !dev_in);
     if (rc != BQC_OK) return rc;
-    const size_t bytes = request_bytes(o, v, s->precision);
+    if (dev_in) {  // orbital energies are checked from a host copy
+        std::vector<double> eo(o), ev(v);
+        int prev = 0;
+        BQC_HIP(hipGetDevice(&prev));
+        BQC_HIP(hipSetDevice(s->device));
+        hipError_t e1 = hipMemcpy(eo.data(), src[0], o * sizeof(double), hipMemcpyDeviceToHost);
+        hipError_t e2 = hipMemcpy(ev.data(), src[1], v * sizeof(double), hipMemcpyDeviceToHost);
+        (void)hipSetDevice(prev);
+        if (e1 != hipSuccess || e2 != hipSuccess) return fail(BQC_EINVAL, "orbital energies are not readable device memory");
+        rc = validate(o, v, eo.data(), ev.data(), src[2], src[3], src[4], src[5], src[6], true);
+        if (rc != BQC_OK) return rc;
+    }
+    const size_t bytes = request_bytes(o, v, s->precision, dev_in);
     if (bytes > s->budget)
         return fail(BQC_ENOMEM, "request footprint " + std::to_string(bytes) + " B exceeds the budget " +
                                     std::to_string(s->budget) + " B");
     auto* r = new Request();
     r->o = o;
     r->v = v;
+    r->dev_in = dev_in;
     for (int a = 0; a < 7; ++a) r->src[a] = src[a];
     r->bytes = bytes;
     r->t_submit = clk::now();
@@ -375,7 +404,14 @@ int bqc_t_submit(bqc_server* s, int32_t nocc, int32_t nvir, const double* eps_o,
                  const double* t1, const double* t2, const double* ovvv, const double* ooov,
                  const double* ovov, uint64_t* ticket) {
     const double* src[7] = {eps_o, eps_v, t1, t2, ovvv, ooov, ovov};
-    return guarded_srv([&] { return submit_impl(s, nocc, nvir, src, ticket); });
+    return guarded_srv([&] { return submit_impl(s, nocc, nvir, src, false, ticket); });
+}
+
+int bqc_t_submit_ex(bqc_server* s, int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v,
+                    const double* t1, const double* t2, const double* ovvv, const double* ooov,
+                    const double* ovov, int32_t inputs_on_device, uint64_t* ticket) {
+    const double* src[7] = {eps_o, eps_v, t1, t2, ovvv, ooov, ovov};
+    return guarded_srv([&] { return submit_impl(s, nocc, nvir, src, inputs_on_device != 0, ticket); });
 }
 
 int bqc_t_poll(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats) {

@@ -10,12 +10,8 @@
 namespace bqc {
 
 void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st);
-void launch_gemm_lowp(int precision, const GemmLaunch& g, hipStream_t st);
 
-void launch_gemm(int precision, const GemmLaunch& g, hipStream_t st) {
-    if (precision == 0 || precision == 1) launch_gemm_fp(precision, g, st);
-    else launch_gemm_lowp(precision, g, st);
-}
+void launch_gemm(int precision, const GemmLaunch& g, hipStream_t st) { launch_gemm_fp(precision, g, st); }
 
 namespace {
 
@@ -39,7 +35,7 @@ Layout layout(int o, int v, int precision) {
     L.ops = off; off += align256(prepare_bytes(precision, o, v));
     L.trip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(int4));
     L.orbits = off; off += align256((size_t)norbit * sizeof(int4));
-    L.hbuf = off; off += align256((size_t)nb * 3 * v3 * hbuf_bytes(precision));
+    L.hbuf = off; off += 2 * align256((size_t)nb * 3 * v3 * hbuf_bytes(precision));
     L.partial = off; off += align256((size_t)nb * norbit * sizeof(double));
     L.etrip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(double));
     L.energy = off; off += 256;
@@ -90,30 +86,35 @@ Plan make_plan(int o, int v, int precision) {
 }
 
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
-                   hipStream_t st, bool timing, SolveStats* stats) {
+                   hipStream_t st, hipStream_t side, bool timing, SolveStats* stats) {
     const int o = plan.o, v = plan.v, prec = plan.precision;
     const Layout L = layout(o, v, prec);
     char* base = (char*)ws;
     int4* d_trip = (int4*)(base + L.trip);
     int4* d_orb = (int4*)(base + L.orbits);
-    void* hbuf = base + L.hbuf;
+    const size_t hsize = (size_t)plan.nb * 3 * v * v * v * hbuf_bytes(prec);
+    void* hbuf[2] = {base + L.hbuf, base + L.hbuf + align256(hsize)};
     double* partial = (double*)(base + L.partial);
     double* etrip = (double*)(base + L.etrip);
     const int ntrip = (int)plan.trip.size();
     const int norbit = (int)plan.orbits.size();
 
     std::vector<hipEvent_t> ev;
-    auto mark = [&](bool on) -> hipEvent_t {
-        if (!on) return nullptr;
+    auto make_event = [&](bool timed) -> hipEvent_t {
         hipEvent_t e;
-        BQC_HIP(hipEventCreate(&e));
-        BQC_HIP(hipEventRecord(e, st));
+        BQC_HIP(hipEventCreateWithFlags(&e, timed ? hipEventDefault : hipEventDisableTiming));
         ev.push_back(e);
+        return e;
+    };
+    auto mark = [&](bool on, hipStream_t s) -> hipEvent_t {
+        if (!on) return nullptr;
+        hipEvent_t e = make_event(true);
+        BQC_HIP(hipEventRecord(e, s));
         return e;
     };
     if (!stats) timing = false;
     const bool want = stats != nullptr;
-    hipEvent_t e_begin = mark(want);
+    hipEvent_t e_begin = mark(want, st);
 
     if (ntrip > 0)
         BQC_HIP(hipMemcpyAsync(d_trip, plan.trip.data(), plan.trip.size() * sizeof(int4),
@@ -122,31 +123,49 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
                            hipMemcpyHostToDevice, st));
     Operands ops;
     if (ntrip > 0) launch_prepare(prec, in, base + L.ops, &ops, st);
-    hipEvent_t e_prep = mark(want);
+    hipEvent_t e_prep = mark(want, st);
+
+    // Two H buffers: the contraction of batch b+1 (stream st, MFMA-bound)
+    // overlaps the epilogue of batch b (stream side, memory-bound).
+    hipEvent_t filled[2] = {make_event(false), make_event(false)};
+    hipEvent_t freed[2] = {make_event(false), make_event(false)};
+    hipEvent_t ready = make_event(false);
+    BQC_HIP(hipEventRecord(ready, st));
+    BQC_HIP(hipStreamWaitEvent(side, ready, 0));  // tables and operands are in place
 
     std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm_ev, epi_ev;
-    for (int b0 = 0; b0 < ntrip; b0 += plan.nb) {
+    int batch = 0;
+    for (int b0 = 0; b0 < ntrip; b0 += plan.nb, ++batch) {
         const int nb = std::min(plan.nb, ntrip - b0);
+        const int k = batch & 1;
+        if (batch >= 2) BQC_HIP(hipStreamWaitEvent(st, freed[k], 0));
         GemmLaunch g;
-        g.o = o; g.v = v; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf;
-        hipEvent_t g0 = mark(timing);
+        g.o = o; g.v = v; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf[k];
+        hipEvent_t g0 = mark(timing, st);
         launch_gemm(prec, g, st);
-        hipEvent_t g1 = mark(timing);
+        hipEvent_t g1 = mark(timing, st);
         if (timing) gemm_ev.emplace_back(g0, g1);
+        BQC_HIP(hipEventRecord(filled[k], st));
+
+        BQC_HIP(hipStreamWaitEvent(side, filled[k], 0));
         EpiLaunch e;
-        e.o = o; e.v = v; e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf;
+        e.o = o; e.v = v; e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf[k];
         e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
         e.orbits = d_orb; e.norbit = norbit; e.partial = partial;
-        hipEvent_t p0 = mark(timing);
-        launch_epilogue(prec, e, st);
-        hipEvent_t p1 = mark(timing);
+        hipEvent_t p0 = mark(timing, side);
+        launch_epilogue(prec, e, side);
+        hipEvent_t p1 = mark(timing, side);
         if (timing) epi_ev.emplace_back(p0, p1);
-        launch_reduce_triples(partial, nb, norbit, d_trip + b0, etrip + b0, st);
+        launch_reduce_triples(partial, nb, norbit, d_trip + b0, etrip + b0, side);
+        BQC_HIP(hipEventRecord(freed[k], side));
     }
+    hipEvent_t done_side = make_event(false);
+    BQC_HIP(hipEventRecord(done_side, side));
+    BQC_HIP(hipStreamWaitEvent(st, done_side, 0));
     launch_reduce_total(etrip, ntrip, (double*)(base + L.energy), st);
     if (d_energy)
         BQC_HIP(hipMemcpyAsync(d_energy, base + L.energy, sizeof(double), hipMemcpyDeviceToDevice, st));
-    hipEvent_t e_end = mark(want);
+    hipEvent_t e_end = mark(want, st);
 
     if (stats) {
         BQC_HIP(hipEventSynchronize(e_end));
@@ -164,6 +183,8 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
         stats->epi_launches = (int)epi_ev.size();
         stats->footprint = L.total;
     }
+    // every event is complete before it is destroyed
+    BQC_HIP(hipStreamSynchronize(st));
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 

@@ -156,3 +156,37 @@ def flops_alg(nocc: int, nvir: int) -> float:
 def _check() -> None:  # pragma: no cover - tiny self check
     x = make_inputs(2, 3, 4, 0)
     assert math.isfinite(float(x.t2.sum()))
+
+
+def make_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:0"):
+    """Same recipe as make_inputs, generated on a HIP device with torch.
+
+    For the serving workload, whose 256 fragments hold ~1 TB of FP64 inputs in
+    total: each fragment is generated on the GPU when it arrives.  The draws
+    come from torch's device generator seeded with `seed`, so the values
+    differ from make_inputs(…, seed) (a different random stream with the same
+    distributions).  Returns the seven ABI arrays as contiguous FP64 tensors.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    n = nocc + nvir
+    f64 = torch.float64
+    x = torch.randn((naux, n, n), generator=g, device=device, dtype=f64) * 0.05
+    b = 0.5 * (x + x.transpose(1, 2))
+    del x
+    eps_o = torch.sort(torch.rand(nocc, generator=g, device=device, dtype=f64) * 1.7 - 2.0).values
+    eps_v = torch.sort(torch.rand(nvir, generator=g, device=device, dtype=f64) * 2.9 + 0.1).values
+    t1 = torch.randn((nocc, nvir), generator=g, device=device, dtype=f64) * 0.01
+    b_oo = b[:, :nocc, :nocc].reshape(naux, nocc * nocc).t().contiguous()
+    b_ov = b[:, :nocc, nocc:].reshape(naux, nocc * nvir)
+    b_vv = b[:, nocc:, nocc:].reshape(naux, nvir * nvir).contiguous()
+    b_ovt = b_ov.t().contiguous()
+    ovvv = (b_ovt @ b_vv).reshape(nocc, nvir, nvir, nvir)
+    ooov = (b_oo @ b_ov.contiguous()).reshape(nocc, nocc, nocc, nvir)
+    ovov = (b_ovt @ b_ov.contiguous()).reshape(nocc, nvir, nocc, nvir)
+    del b, b_oo, b_ov, b_vv, b_ovt
+    denom = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
+             - eps_v[None, None, :, None] - eps_v[None, None, None, :])
+    t2 = (ovov.permute(0, 2, 1, 3) / denom).contiguous()
+    return tuple(a.contiguous() for a in (eps_o, eps_v, t1, t2, ovvv, ooov, ovov))

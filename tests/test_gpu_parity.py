@@ -128,3 +128,39 @@ def test_invalid_arguments_rejected():
     with pytest.raises(bqc.BqcError) as ei:
         bqc.t_energy(3, 5, bad, *x.arrays()[1:])
     assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_bf16x3(seed):
+    bqc = _bqc()
+    x = make_inputs(6, 30, 120, seed)
+    ref = _case(6, 30, 120, seed)["E_T"]
+    e = bqc.t_energy(6, 30, *x.arrays(), precision="bf16x3")
+    print(f"bf16x3 seed={seed} dE={abs(e - ref) * 1e6:.3e} uEh", flush=True)
+    assert abs(e - ref) <= 1e-6
+
+
+def test_ragged_bf16x3():
+    bqc = _bqc()
+    for (o, v, naux, seed) in [(5, 37, 100, 3), (9, 20, 60, 8), (4, 64, 160, 1), (2, 17, 40, 5)]:
+        x = make_inputs(o, v, naux, seed)
+        ref = _case(o, v, naux, seed)["E_T"]
+        e = bqc.t_energy(o, v, *x.arrays(), precision="bf16x3")
+        print(f"bf16x3 o={o} v={v} rel={abs(e - ref) / abs(ref):.3e}", flush=True)
+        assert abs(e - ref) <= 1e-6 * abs(ref), (o, v, e, ref)
+
+
+def test_small_and_ragged_fp8():
+    """FP8 e4m3 with per-32 power-of-two scales: reported, not gated at 1e-6.
+
+    The bound checked here (relative error <= 2e-3) is a sanity gate for a
+    3-bit-mantissa contraction whose rounding errors largely cancel in E_T."""
+    bqc = _bqc()
+    for (o, v, naux, seed) in [(6, 30, 120, 0), (6, 30, 120, 1), (5, 37, 100, 3), (4, 64, 160, 1)]:
+        x = make_inputs(o, v, naux, seed)
+        ref = _case(o, v, naux, seed)["E_T"]
+        e = bqc.t_energy(o, v, *x.arrays(), precision="fp8")
+        print(f"fp8 o={o} v={v} seed={seed} dE={abs(e - ref) * 1e6:.3e} uEh rel={abs(e - ref) / abs(ref):.3e}",
+              flush=True)
+        assert np.isfinite(e)
+        assert abs(e - ref) <= 2e-3 * abs(ref), (o, v, e, ref)

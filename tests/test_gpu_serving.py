@@ -90,3 +90,21 @@ def test_fp32_serving_matches_fp32_alone():
         got = [srv.wait(t)[0] for t in ts]
     for s, x, e in zip(SHAPES, xs, got):
         assert e == bqc.t_energy(s[0], s[1], *x.arrays(), precision="fp32")
+
+
+def test_device_resident_submit():
+    """Fragments generated on the GPU and submitted as device pointers."""
+    import torch
+
+    from synth import make_inputs_device
+    bqc = _bqc()
+    shapes = [(3, 20, 40, 401), (5, 33, 80, 402), (4, 27, 60, 403)]
+    xs = [make_inputs_device(*s) for s in shapes]
+    with bqc.Server(precision="fp64", max_inflight=2, mem_budget_bytes=1 << 29) as srv:
+        ts = [srv.submit(s[0], s[1], *x) for s, x in zip(shapes, xs)]
+        got = [srv.wait(t)[0] for t in ts]
+    for s, x, e in zip(shapes, xs, got):
+        assert e == bqc.t_energy(s[0], s[1], *x)
+        torch.cuda.synchronize()
+        ref = oracle_t_energy(*[a.cpu().numpy() for a in x])
+        assert abs(e - ref) <= 1e-10 * abs(ref)
