@@ -131,7 +131,8 @@ typedef struct {
     int32_t  precision;        /* bqc_precision for every request */
     uint64_t mem_budget_bytes; /* 0: 85% of the device's free memory at creation */
     int32_t  max_inflight;     /* 0: 4 */
-    int32_t  n_streams;        /* 0: max_inflight */
+    int32_t  direct_launch;    /* 0: each request's triple-batch launch sequence is captured into one
+                                  hipGraph and launched as a unit; 1: kernels are launched one by one */
 } bqc_server_cfg;
 
 /* Creates a server; *out is written on BQC_OK. */

@@ -47,7 +47,7 @@ class TStats(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
-                ("n_streams", ctypes.c_int32)]
+                ("direct_launch", ctypes.c_int32)]
 
 
 class BqcError(RuntimeError):
@@ -206,8 +206,9 @@ class Server:
     status (the C ABI borrows them until then).
     """
 
-    def __init__(self, precision="fp64", device=0, mem_budget_bytes=0, max_inflight=0):
+    def __init__(self, precision="fp64", device=0, mem_budget_bytes=0, max_inflight=0, graphs=True):
         cfg = ServerCfg()
+        cfg.direct_launch = 0 if graphs else 1
         cfg.device = device
         cfg.precision = _prec(precision)
         cfg.mem_budget_bytes = int(mem_budget_bytes)

@@ -118,6 +118,7 @@ void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* 
 int64_t prepare_bytes(int precision, int o, int v);
 
 void launch_gemm(int precision, const GemmLaunch& g, hipStream_t st);
+int wave_blocks(int v);  // contraction wave tile (16-blocks per side) used for this v
 void launch_epilogue(int precision, const EpiLaunch& e, hipStream_t st);
 void launch_reduce_triples(const double* partial, int ntrip, int norbit, const int4* trip,
                            double* e_trip, hipStream_t st);
@@ -152,8 +153,10 @@ Plan make_plan(int o, int v, int precision);
 // workspace (workspace_energy / workspace_etrip).
 // `side` is a second stream of the same device on which the epilogues run,
 // overlapping the contractions on `st`; everything is ordered back onto `st`.
-// Returns after `st` has drained (the solve is complete).
+// Returns after `st` has drained (the solve is complete).  graph = true
+// captures the batch sequence into a hipGraph and launches it as one unit
+// (no per-kernel timing then).
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
-                   hipStream_t st, hipStream_t side, bool timing, SolveStats* stats);
+                   hipStream_t st, hipStream_t side, bool timing, SolveStats* stats, bool graph = false);
 
 }  // namespace bqc

@@ -7,9 +7,11 @@
 // {A, B, C} (A >= B >= C, tiles of EPI_T virtuals), the work group builds in
 // LDS, for the six tile permutations s(A, B, C),
 //   W = H_a[a][b][c] + H_b[b][a][c] + H_c[c][a][b]            (six-fold P)
+// together with the 8 x 8 blocks of (jb|kc), (ia|kc), (ia|jb) and the t1
+// slices the orbit needs, and every thread takes one element (a, b, c) of the
+// base tile with its six permutations p, forming
 //   V = W + t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)       (singles term)
-// and every thread takes one element (a, b, c) of the base tile with its
-// six permutations p.  With D = e_i + e_j + e_k - e_a - e_b - e_c (the same
+// on the fly.  With D = e_i + e_j + e_k - e_a - e_b - e_c (the same
 // for all six) the numerator operator 4 + cyclic - 2 transpositions acting on
 // V gives, for even p:  3 V_p + S_e - 2 S_o  and for odd p:  3 V_p + S_o - 2 S_e
 // (S_e, S_o = sums of V over even and odd permutations), so
@@ -47,79 +49,80 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     const HT* Ha = (const HT*)e.hbuf + (int64_t)(t * 3 + 0) * v3;
     const HT* Hb = Ha + v3;
     const HT* Hc = Hb + v3;
-    const double* t1i = e.t1 + (int64_t)i * v;
-    const double* t1j = e.t1 + (int64_t)j * v;
-    const double* t1k = e.t1 + (int64_t)k * v;
-    // (jb|kc) = ovov[j][b][k][c] etc.: row stride o*v within the j block
     const int64_t ov = (int64_t)e.o * v;
-    const double* g_jk = e.ovov + (int64_t)j * v * ov + (int64_t)k * v;
-    const double* g_ik = e.ovov + (int64_t)i * v * ov + (int64_t)k * v;
-    const double* g_ij = e.ovov + (int64_t)i * v * ov + (int64_t)j * v;
 
+    constexpr int T = EPI_T, T2 = EPI_T * EPI_T;
     __shared__ double Ws[6][E_T3];
-    __shared__ double Vs[6][E_T3];
+    // singles-term factors of the orbit's tiles: G[m][X][Y][x][y] with
+    // m = 0: (jb|kc), 1: (ia|kc), 2: (ia|jb), X, Y tile ids in {A, B, C};
+    // t1s[n][X][x] = t_{i,j,k}^{tile X, x}
+    __shared__ double Gs[3][3][3][T2];
+    __shared__ double t1s[3][3][T];
     __shared__ double red[E_THREADS / 64];
 
-    // tile permutations: 0 (A,B,C) 1 (A,C,B) 2 (B,A,C) 3 (B,C,A) 4 (C,A,B) 5 (C,B,A)
-    const int TA = ob.x, TB = ob.y, TC = ob.z;
-    const int tiles[6][3] = {{TA, TB, TC}, {TA, TC, TB}, {TB, TA, TC},
-                             {TB, TC, TA}, {TC, TA, TB}, {TC, TB, TA}};
+    const int TT[3] = {ob.x, ob.y, ob.z};  // tile ids 0, 1, 2 -> tiles A, B, C
+    // tile permutations as tile ids: 0 (A,B,C) 1 (A,C,B) 2 (B,A,C) 3 (B,C,A) 4 (C,A,B) 5 (C,B,A)
+    const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
-    // pass 1: z-fastest threads read H_a and H_b (contiguous in c) and add the singles term
+    // phase 0: singles-term factors
+    const int occ[3] = {i, j, k};
+    for (int el = threadIdx.x; el < 3 * 9 * T2; el += E_THREADS) {
+        const int m = el / (9 * T2), rem = el % (9 * T2);
+        const int X = rem / (3 * T2), Y = (rem / T2) % 3, xy = rem % T2;
+        const int x = TT[X] * T + xy / T, y = TT[Y] * T + xy % T;
+        // m = 0: (jb|kc) with b in X, c in Y; 1: (ia|kc); 2: (ia|jb)
+        const int p = m == 0 ? j : i, q = m == 2 ? j : k;
+        double g = 0.0;
+        if (x < v && y < v) g = e.ovov[((int64_t)p * v + x) * ov + (int64_t)q * v + y];
+        Gs[m][X][Y][xy] = g;
+    }
+    for (int el = threadIdx.x; el < 3 * 3 * T; el += E_THREADS) {
+        const int n = el / (3 * T), X = (el / T) % 3, x = TT[X] * T + el % T;
+        t1s[n][X][el % T] = x < v ? e.t1[(int64_t)occ[n] * v + x] : 0.0;
+    }
+
+    // phase 1: z-fastest threads read H_a and H_b (contiguous in c)
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
         for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
-            const int x = el / (EPI_T * EPI_T), y = (el / EPI_T) % EPI_T, z = el % EPI_T;
-            const int a = tiles[s][0] * EPI_T + x, b = tiles[s][1] * EPI_T + y,
-                      c = tiles[s][2] * EPI_T + z;
-            double w = 0.0, vv = 0.0;
-            if (a < v && b < v && c < v) {
+            const int x = el / T2, y = (el / T) % T, z = el % T;
+            const int a = TT[perm[s][0]] * T + x, b = TT[perm[s][1]] * T + y, c = TT[perm[s][2]] * T + z;
+            double w = 0.0;
+            if (a < v && b < v && c < v)
                 w = (double)Ha[(int64_t)a * v2 + (int64_t)b * v + c] +
                     (double)Hb[(int64_t)b * v2 + (int64_t)a * v + c];
-                vv = w + t1i[a] * g_jk[(int64_t)b * ov + c] + t1j[b] * g_ik[(int64_t)a * ov + c] +
-                     t1k[c] * g_ij[(int64_t)a * ov + b];
-            }
             Ws[s][el] = w;
-            Vs[s][el] = vv;
         }
     }
     __syncthreads();
-    // pass 2: b-fastest threads read H_c[c][a][b] (contiguous in b)
+    // phase 2: b-fastest threads read H_c[c][a][b] (contiguous in b)
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
         for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
-            const int x = el / (EPI_T * EPI_T), z = (el / EPI_T) % EPI_T, y = el % EPI_T;
-            const int a = tiles[s][0] * EPI_T + x, b = tiles[s][1] * EPI_T + y,
-                      c = tiles[s][2] * EPI_T + z;
-            if (a < v && b < v && c < v) {
-                const double hc = (double)Hc[(int64_t)c * v2 + (int64_t)a * v + b];
-                const int li = (x * EPI_T + y) * EPI_T + z;
-                Ws[s][li] += hc;
-                Vs[s][li] += hc;
-            }
+            const int x = el / T2, z = (el / T) % T, y = el % T;
+            const int a = TT[perm[s][0]] * T + x, b = TT[perm[s][1]] * T + y, c = TT[perm[s][2]] * T + z;
+            if (a < v && b < v && c < v)
+                Ws[s][(x * T + y) * T + z] += (double)Hc[(int64_t)c * v2 + (int64_t)a * v + b];
         }
     }
     __syncthreads();
 
+    // phase 3: one element (a, b, c) of the base tile and its six permutations
     const double eocc = e.eps_o[i] + e.eps_o[j] + e.eps_o[k];
     double acc = 0.0;
     for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
-        const int al = el / (EPI_T * EPI_T), be = (el / EPI_T) % EPI_T, ga = el % EPI_T;
-        const int a = TA * EPI_T + al, b = TB * EPI_T + be, c = TC * EPI_T + ga;
+        const int l[3] = {el / T2, (el / T) % T, el % T};  // locals of a, b, c
+        const int a = TT[0] * T + l[0], b = TT[1] * T + l[1], c = TT[2] * T + l[2];
         if (a >= v || b >= v || c >= v) continue;
-        const int T2 = EPI_T * EPI_T;
-        // element (a,b,c) and its permutations in the six tiles
-        const int idx[6] = {(al * EPI_T + be) * EPI_T + ga,   // (a,b,c) in (A,B,C)
-                            (al * EPI_T + ga) * EPI_T + be,   // (a,c,b) in (A,C,B)
-                            (be * EPI_T + al) * EPI_T + ga,   // (b,a,c) in (B,A,C)
-                            (be * EPI_T + ga) * EPI_T + al,   // (b,c,a) in (B,C,A)
-                            ga * T2 + al * EPI_T + be,        // (c,a,b) in (C,A,B)
-                            ga * T2 + be * EPI_T + al};       // (c,b,a) in (C,B,A)
         double W[6], V[6];
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
-            W[p] = Ws[p][idx[p]];
-            V[p] = Vs[p][idx[p]];
+            // permutation p puts tile ids (X, Y, Z) on the virtual slots a, b, c
+            const int X = perm[p][0], Y = perm[p][1], Z = perm[p][2];
+            const int x = l[X], y = l[Y], z = l[Z];
+            W[p] = Ws[p][(x * T + y) * T + z];
+            V[p] = W[p] + t1s[0][X][x] * Gs[0][Y][Z][y * T + z] + t1s[1][Y][y] * Gs[1][X][Z][x * T + z] +
+                   t1s[2][Z][z] * Gs[2][X][Y][x * T + y];
         }
         const double d = eocc - e.eps_v[a] - e.eps_v[b] - e.eps_v[c];
         const double se = V[0] + V[3] + V[4], so = V[1] + V[2] + V[5];

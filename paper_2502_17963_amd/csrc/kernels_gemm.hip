@@ -25,24 +25,27 @@
 // stored): a branch per MFMA would cost more than the idle blocks.  Operands are staged through LDS in
 // stages of 128 bytes per row (8 16-byte vectors, swizzled so that the
 // fragment reads are free of bank conflicts), double-buffered through
-// registers.  Within a stage, MFMA lane group g (lanes 16g..16g+15) takes the
-// contraction elements [g*KC/4, (g+1)*KC/4), so each fragment is two 16-byte
-// LDS reads; A and B use the same assignment, so every element of the stage
-// is contracted exactly once.
+// registers.  Within a stage, MFMA lane group g (lanes 16g..16g+15) takes
+// the 16-byte units g and 4+g of each staged row (two 16-byte LDS reads per
+// fragment, free of bank conflicts); A and B use the same assignment, so
+// every element of the stage is contracted exactly once.
 #include "bqc_internal.h"
 
 namespace bqc {
 namespace {
 
-constexpr int TB = 10;                 // max 16-blocks per tile side
-constexpr int WB = 5;                  // max 16-blocks per wave side (2 x 2 waves)
-constexpr int TILE = TB * 16;          // 160
-constexpr int NROW = 2 * TILE;         // LDS rows: Row operand, then Col operand
 constexpr int ROWB = 128;              // bytes per LDS row and stage
-constexpr int NTHR = 256;
-constexpr int NVEC = NROW * (ROWB / 16) / NTHR;  // 16-byte vectors per thread per stage
-static_assert(NVEC * NTHR == NROW * 8, "stage loads divide evenly");
-static_assert((NTHR / 8) * (NVEC / 2) == TILE, "half of each thread's vectors are Row rows");
+
+// Work-group geometry: WU x WW waves, each owning up to WB x WB 16x16 blocks,
+// so a tile covers up to WU*WB*16 rows u and WW*WB*16 columns w.
+template <int WU_, int WW_, int WB_>
+struct Geo {
+    static constexpr int WU = WU_, WW = WW_, WB = WB_;
+    static constexpr int TILE_U = WU * WB * 16, TILE_W = WW * WB * 16;
+    static constexpr int NROW = TILE_U + TILE_W;       // LDS rows: Row factor, then Col factor
+    static constexpr int NTHR = 64 * WU * WW;
+    static constexpr int NVEC = (NROW * 8 + NTHR - 1) / NTHR;  // 16-byte vectors per thread per stage
+};
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -92,7 +95,7 @@ typedef int i8v __attribute__((ext_vector_type(8)));
 // Byte offset of 16-byte vector q of LDS row r (XOR swizzle by row pair).
 __device__ __forceinline__ int lds_off(int r, int q) { return r * ROWB + ((q ^ ((r >> 1) & 7)) << 4); }
 
-// Balanced split of nblk 16-blocks into ntile tiles.
+// Balanced split of nblk 16-blocks into ntile parts.
 __device__ __forceinline__ void tile_range(int t, int nblk, int ntile, int& start, int& count) {
     const int base = nblk / ntile, extra = nblk % ntile;
     start = t * base + min(t, extra);
@@ -149,9 +152,10 @@ __device__ __forceinline__ void roles(int h, int i, int j, int k, int& q, int& P
     else { q = k; P = i; R = j; }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile,
-                                                           int per_xcd) {
+template <int PREC, class G>
+__global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile_u,
+                                                              int ntile_w, int per_xcd) {
+    constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, NVEC = G::NVEC, WB = G::WB;
     typedef Mode<PREC> M;
     typedef typename M::E E;
     typedef typename M::Acc Acc;
@@ -165,8 +169,8 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
     if (L >= n_wg) return;
     const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
     int rem = L;
-    const int tw = rem % ntile; rem /= ntile;
-    const int tu = rem % ntile; rem /= ntile;
+    const int tw = rem % ntile_w; rem /= ntile_w;
+    const int tu = rem % ntile_u; rem /= ntile_u;
     const int y = rem % v; rem /= v;
     const int h = rem % 3;
     const int t = rem / 3;
@@ -175,16 +179,16 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
     roles(h, tr.x, tr.y, tr.z, q, P, R);
 
     int ub, un, wb, wn;  // tile block start / count along u and w
-    tile_range(tu, nblk, ntile, ub, un);
-    tile_range(tw, nblk, ntile, wb, wn);
+    tile_range(tu, nblk, ntile_u, ub, un);
+    tile_range(tw, nblk, ntile_w, wb, wn);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wu = wave & 1, ww = wave >> 1;
-    const int uh = (un + 1) >> 1, wh = (wn + 1) >> 1;
-    const int am = wu ? un - uh : uh;       // active row blocks of this wave
-    const int an = ww ? wn - wh : wh;       // active col blocks of this wave
-    const int arow0 = (wu ? uh : 0) * 16;   // first LDS Row-operand row of this wave
-    const int brow0 = TILE + (ww ? wh : 0) * 16;
+    const int wu = wave % G::WU, ww = wave / G::WU;
+    int wub, wun, wwb, wwn;  // this wave's blocks within the tile
+    tile_range(wu, un, G::WU, wub, wun);
+    tile_range(ww, wn, G::WW, wwb, wwn);
+    const int arow0 = wub * 16;           // first LDS Row-factor row of this wave
+    const int brow0 = TILE_U + wwb * 16;  // first LDS Col-factor row of this wave
 
     __shared__ __attribute__((aligned(16))) char lds[2][NROW * ROWB];
     // FP8 only: the E8M0 exponent word (4 x 32 elements) of every staged row
@@ -197,18 +201,19 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
         for (int b = 0; b < WB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
     // This thread's 16-byte vector qv of each staged row, and its rows: vector
-    // e covers LDS row (tid / 8) + 32 e; rows [0, TILE) hold the Row factor
-    // (u), rows [TILE, 2 TILE) the Col factor (w).  Byte offsets within a
-    // chunk block are fixed for the work group.
+    // e covers LDS row (tid / 8) + e NTHR / 8; rows [0, TILE_U) hold the Row
+    // factor (u), rows [TILE_U, NROW) the Col factor (w).  Byte offsets
+    // within a chunk block are fixed for the work group.
     const int qv = tid & 7;
     int off[NVEC];
-    bool ok[NVEC];
+    bool ok[NVEC], isrow[NVEC];
 #pragma unroll
     for (int e = 0; e < NVEC; ++e) {
         const int row = (tid >> 3) + e * (NTHR / 8);
-        const int r = e < NVEC / 2 ? row : row - TILE;
-        const int gr = (e < NVEC / 2 ? ub : wb) * 16 + r;
-        ok[e] = r < (e < NVEC / 2 ? un : wn) * 16 && gr < v;
+        isrow[e] = row < TILE_U;
+        const int r = isrow[e] ? row : row - TILE_U;
+        const int gr = (isrow[e] ? ub : wb) * 16 + r;
+        ok[e] = row < NROW && r < (isrow[e] ? un : wn) * 16 && gr < v;
         off[e] = gr * ROWB + qv * 16;
     }
 
@@ -230,10 +235,10 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
 #pragma unroll
         for (int e = 0; e < NSROW; ++e) {
             const int row = tid + e * NTHR;
-            const bool isrow = row < TILE;
-            const int r = isrow ? row : row - TILE;
-            const int gr = (isrow ? ub : wb) * 16 + r;
-            srow_ok[e] = row < NROW && r < (isrow ? un : wn) * 16 && gr < v;
+            const bool isr = row < TILE_U;
+            const int r = isr ? row : row - TILE_U;
+            const int gr = (isr ? ub : wb) * 16 + r;
+            srow_ok[e] = row < NROW && r < (isr ? un : wn) * 16 && gr < v;
             srow_g[e] = gr;
         }
     }
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
         const char* cb = arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * blk;
 #pragma unroll
         for (int e = 0; e < NVEC; ++e) {
-            const char* base = e < NVEC / 2 ? rb : cb;
+            const char* base = isrow[e] ? rb : cb;
             reg[e] = ok[e] ? *(const u4*)(base + off[e]) : u4{0, 0, 0, 0};
         }
         if constexpr (PREC == 3) {
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
 #pragma unroll
             for (int e = 0; e < NSROW; ++e) {
                 const int row = tid + e * NTHR;
-                sreg[e] = srow_ok[e] ? (row < TILE ? rs : cs)[srow_g[e]] : 0u;
+                sreg[e] = srow_ok[e] ? (row < TILE_U ? rs : cs)[srow_g[e]] : 0u;
             }
         }
     };
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
 #pragma unroll
         for (int e = 0; e < NVEC; ++e) {
             const int row = (tid >> 3) + e * (NTHR / 8);
-            *(u4*)(&lds[buf][lds_off(row, qv)]) = reg[e];
+            if ((NVEC * NTHR == NROW * 8) || row < NROW) *(u4*)(&lds[buf][lds_off(row, qv)]) = reg[e];
         }
         if constexpr (PREC == 3) {
 #pragma unroll
@@ -280,17 +285,21 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
     auto compute = [&](int buf) {
         const char* L0 = lds[buf];
         if constexpr (PREC == 3) {
-            // lane group g holds elements [32 g, 32 g + 32) of its row and the
-            // exponent byte g of the row's scale word
+            // The FP8 16x16x128 MFMA reads lane group g's 32 bytes as
+            // contraction elements [16g, 16g+16) and [64+16g, 64+16g+16) and
+            // takes from lane group g the exponent of elements [32g, 32g+32).
+            // Feeding units g and 4+g of the staged row places every staged
+            // 32-element block b (units 2b, 2b+1) exactly in the MFMA's block
+            // b, whose exponent, byte b of the row's scale word, group b holds.
             i8v af[WB], bfr[WB];
             int sa[WB], sb[WB];
 #pragma unroll
             for (int m = 0; m < WB; ++m) {
                 const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-                const u4 a0 = *(const u4*)(L0 + lds_off(ra, 2 * fg));
-                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 2 * fg + 1));
-                const u4 b0 = *(const u4*)(L0 + lds_off(rb, 2 * fg));
-                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 2 * fg + 1));
+                const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
+                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
+                const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
+                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
                 af[m] = i8v{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
                 bfr[m] = i8v{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
                 sa[m] = (int)((lds_s[buf][ra] >> (8 * fg)) & 0xffu);
@@ -333,10 +342,10 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
 #pragma unroll
             for (int m = 0; m < WB; ++m) {
                 const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-                const u4 a0 = *(const u4*)(L0 + lds_off(ra, 2 * fg));
-                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 2 * fg + 1));
-                const u4 b0 = *(const u4*)(L0 + lds_off(rb, 2 * fg));
-                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 2 * fg + 1));
+                const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
+                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
+                const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
+                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
                 const E* pa0 = (const E*)&a0; const E* pa1 = (const E*)&a1;
                 const E* pb0 = (const E*)&b0; const E* pb1 = (const E*)&b1;
 #pragma unroll
@@ -373,12 +382,12 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
 
     const int64_t v2 = (int64_t)v * v;
     HT* out = (HT*)g.hbuf + ((int64_t)(t * 3 + h) * v + y) * v2;
-    const int u00 = ub * 16 + (wu ? uh : 0) * 16, w00 = wb * 16 + (ww ? wh : 0) * 16;
+    const int u00 = (ub + wub) * 16, w00 = (wb + wwb) * 16;
 #pragma unroll
     for (int m = 0; m < WB; ++m)
 #pragma unroll
         for (int nn = 0; nn < WB; ++nn)
-            if (m < am && nn < an) {
+            if (m < wun && nn < wwn) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int u = u00 + m * 16 + M::row(lane, r);
@@ -390,29 +399,66 @@ __global__ __launch_bounds__(NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg,
 
 }  // namespace
 
-void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st) {
+namespace {
+
+template <int PREC, class G>
+void launch_geo(const GemmLaunch& g, hipStream_t st) {
     const int nblk = ceil_div(g.v, 16);
-    const int ntile = ceil_div(nblk, TB);
-    const int64_t n64 = (int64_t)g.ntrip * 3 * g.v * ntile * ntile;
+    const int ntile_u = ceil_div(nblk, G::WU * G::WB), ntile_w = ceil_div(nblk, G::WW * G::WB);
+    const int64_t n64 = (int64_t)g.ntrip * 3 * g.v * ntile_u * ntile_w;
     if (n64 > ((int64_t)1 << 31) - 8) throw Error(-1, "contraction grid too large");
     const int n_wg = (int)n64;
     const int per_xcd = ceil_div(n_wg, 8);
-    dim3 grid(per_xcd * 8), block(NTHR);
+    hipLaunchKernelGGL((h_gemm_kernel<PREC, G>), dim3(per_xcd * 8), dim3(G::NTHR), 0, st, g, n_wg, nblk,
+                       ntile_u, ntile_w, per_xcd);
+}
+
+// Share of the computed 16x16 block products that are useful when the nblk
+// blocks of v are split over tiles of 2 x 2 waves of at most wb x wb blocks.
+double block_use(int nblk, int wb) {
+    const int ntile = ceil_div(nblk, 2 * wb);
+    const double slots = (double)ntile * ntile * 4 * wb * wb;
+    return (double)nblk * nblk / slots;
+}
+
+template <int PREC>
+void launch_mode(const GemmLaunch& g, hipStream_t st) {
+    const int wb = wave_blocks(g.v);
+    switch (wb) {
+        case 2: launch_geo<PREC, Geo<2, 2, 2>>(g, st); break;
+        case 3: launch_geo<PREC, Geo<2, 2, 3>>(g, st); break;
+        case 4: launch_geo<PREC, Geo<2, 2, 4>>(g, st); break;
+        default: launch_geo<PREC, Geo<2, 2, 5>>(g, st); break;
+    }
+}
+
+}  // namespace
+
+// Wave tile size (blocks per side) for this v: a smaller tile wastes fewer
+// block products on partial tiles but loads more operand bytes per flop, so
+// it is taken only when its useful share is at least 20% higher.
+int wave_blocks(int v) {
+    const int nblk = ceil_div(v, 16);
+    int best = 5;
+    double use = block_use(nblk, 5);
+    for (int wb = 4; wb >= 2; --wb) {
+        const double u = block_use(nblk, wb);
+        if (u > 1.2 * use) { use = u; best = wb; }
+    }
+    return best;
+}
+
+// Work groups of 2 x 2 waves; the wave tile is chosen per v (wave_blocks).
+// A 320 x 160 tile with 8 waves loads a quarter fewer operand bytes per flop
+// than 160 x 160 but measured slower (FP32 7.9 s vs 7.6 s, BF16x3 3.7 s vs
+// 3.4 s per solve at o = 32, v = 300).
+void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st) {
     switch (precision) {
-        case 0:
-            hipLaunchKernelGGL(h_gemm_kernel<0>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
-            break;
-        case 1:
-            hipLaunchKernelGGL(h_gemm_kernel<1>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
-            break;
-        case 2:
-            hipLaunchKernelGGL(h_gemm_kernel<2>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
-            break;
-        case 3:
-            hipLaunchKernelGGL(h_gemm_kernel<3>, grid, block, 0, st, g, n_wg, nblk, ntile, per_xcd);
-            break;
-        default:
-            throw Error(-1, "unsupported precision for the MFMA contraction");
+        case 0: launch_mode<0>(g, st); break;
+        case 1: launch_mode<1>(g, st); break;
+        case 2: launch_mode<2>(g, st); break;
+        case 3: launch_mode<3>(g, st); break;
+        default: throw Error(-1, "unsupported precision for the MFMA contraction");
     }
     BQC_HIP(hipGetLastError());
 }

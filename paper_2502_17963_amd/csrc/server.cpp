@@ -11,7 +11,9 @@
 //     (a request may be overtaken by smaller ones at most kMaxBypass times,
 //     after which admission waits for it), uploads it, enqueues its whole
 //     solve on its stream and waits for it, so that admitted requests run
-//     concurrently on the device while new ones keep arriving.
+//     concurrently on the device while new ones keep arriving.  By default
+//     the request's triple-batch launch sequence is captured into one hipGraph
+//     and launched as a unit.
 // A request's launch sequence is the one bqc_t_energy_ex uses, so its result
 // is bitwise identical alone and in the mix.
 #include <algorithm>
@@ -103,6 +105,7 @@ struct Request {
 
 struct bqc_server {
     int device = 0, precision = 0, max_inflight = 4;
+    bool graphs = true;  // capture each request's launch sequence into a hipGraph
     uint64_t budget = 0;
     void* arena_base = nullptr;
     bqc::Arena* arena = nullptr;
@@ -154,7 +157,7 @@ int run_request(bqc_server* s, Request* r, hipStream_t st, hipStream_t side, dou
     in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
     const Plan plan = make_plan(o, v, s->precision);
     SolveStats ss;
-    enqueue_solve(plan, in, ws, nullptr, st, side, false, &ss);
+    enqueue_solve(plan, in, ws, nullptr, st, side, false, &ss, s->graphs);
     BQC_HIP(hipMemcpyAsync(pinned, workspace_energy(ws, o, v, s->precision), sizeof(double),
                            hipMemcpyDeviceToHost, st));
     BQC_HIP(hipStreamSynchronize(st));
@@ -245,6 +248,7 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
     s->device = cfg->device;
     s->precision = cfg->precision;
     s->max_inflight = cfg->max_inflight > 0 ? cfg->max_inflight : 4;
+    s->graphs = cfg->direct_launch == 0;
     try {
         size_t fr = 0, tot = 0;
         BQC_HIP(hipMemGetInfo(&fr, &tot));

@@ -86,7 +86,7 @@ Plan make_plan(int o, int v, int precision) {
 }
 
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
-                   hipStream_t st, hipStream_t side, bool timing, SolveStats* stats) {
+                   hipStream_t st, hipStream_t side, bool timing, SolveStats* stats, bool graph) {
     const int o = plan.o, v = plan.v, prec = plan.precision;
     const Layout L = layout(o, v, prec);
     char* base = (char*)ws;
@@ -112,7 +112,7 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
         BQC_HIP(hipEventRecord(e, s));
         return e;
     };
-    if (!stats) timing = false;
+    if (!stats || graph) timing = false;
     const bool want = stats != nullptr;
     hipEvent_t e_begin = mark(want, st);
 
@@ -129,6 +129,9 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     // overlaps the epilogue of batch b (stream side, memory-bound).
     hipEvent_t filled[2] = {make_event(false), make_event(false)};
     hipEvent_t freed[2] = {make_event(false), make_event(false)};
+    // Graph mode: the whole batch sequence (both streams) is captured from
+    // `st` into one graph and launched as a unit.
+    if (graph) BQC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipEvent_t ready = make_event(false);
     BQC_HIP(hipEventRecord(ready, st));
     BQC_HIP(hipStreamWaitEvent(side, ready, 0));  // tables and operands are in place
@@ -163,6 +166,21 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     BQC_HIP(hipEventRecord(done_side, side));
     BQC_HIP(hipStreamWaitEvent(st, done_side, 0));
     launch_reduce_total(etrip, ntrip, (double*)(base + L.energy), st);
+    if (graph) {
+        hipGraph_t gr = nullptr;
+        BQC_HIP(hipStreamEndCapture(st, &gr));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            BQC_HIP(ie);
+        }
+        const hipError_t le = hipGraphLaunch(ex, st);
+        const hipError_t se = le == hipSuccess ? hipStreamSynchronize(st) : le;
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(gr);
+        BQC_HIP(se);
+    }
     if (d_energy)
         BQC_HIP(hipMemcpyAsync(d_energy, base + L.energy, sizeof(double), hipMemcpyDeviceToDevice, st));
     hipEvent_t e_end = mark(want, st);

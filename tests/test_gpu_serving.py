@@ -108,3 +108,14 @@ def test_device_resident_submit():
         torch.cuda.synchronize()
         ref = oracle_t_energy(*[a.cpu().numpy() for a in x])
         assert abs(e - ref) <= 1e-10 * abs(ref)
+
+
+def test_graph_and_direct_launch_agree():
+    bqc = _bqc()
+    xs = [make_inputs(*s) for s in SHAPES[:5]]
+    out = {}
+    for graphs in (True, False):
+        with bqc.Server(precision="fp64", max_inflight=3, mem_budget_bytes=1 << 30, graphs=graphs) as srv:
+            ts = [srv.submit(s[0], s[1], *x.arrays()) for s, x in zip(SHAPES, xs)]
+            out[graphs] = [srv.wait(t)[0] for t in ts]
+    assert out[True] == out[False]
