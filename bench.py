@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--workload", default="large_fragment",
                     choices=["small", "large_fragment", "precision_sweep", "largest_fragment", "serving",
                              "copy_calibration"])
-    ap.add_argument("--precisions", default="fp32",
+    ap.add_argument("--precisions", default="fp32,bf16x3,fp8",
                     help="comma list of candidate contraction precisions for the headline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
