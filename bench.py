@@ -152,6 +152,9 @@ def _serve_stream(bqc, srv, shapes, arrivals, cap_bytes, keep_idx):
             del pending[t]
         if done:
             torch.cuda.empty_cache()
+            if len(rec) % 8 == 0 or len(rec) == len(shapes):
+                print(f"[serving] {len(rec)}/{len(shapes)} done at {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
         elif nxt >= len(shapes) or arrivals[nxt] > now:
             time.sleep(0.002)
     return rec, time.perf_counter() - t0, kept

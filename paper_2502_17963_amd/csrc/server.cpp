@@ -119,6 +119,8 @@ struct bqc_server {
     std::vector<double*> pinned;
     bool stop = false;
     uint64_t next_ticket = 1;
+    hipStream_t check_stream = nullptr;  // reads device orbital energies at submit
+    std::mutex check_mu;
 };
 
 namespace bqc {
@@ -255,6 +257,7 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
         s->budget = cfg->mem_budget_bytes ? cfg->mem_budget_bytes : (uint64_t)(0.85 * (double)fr);
         s->budget &= ~(uint64_t)255;
         BQC_HIP(hipMalloc(&s->arena_base, s->budget));
+        BQC_HIP(hipStreamCreateWithFlags(&s->check_stream, hipStreamNonBlocking));
         s->arena = new Arena(s->budget);
         for (int k = 0; k < s->max_inflight; ++k) {
             hipStream_t st;
@@ -271,6 +274,7 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
         (void)hipSetDevice(prev);
         for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
         for (hipStream_t st : s->sides) (void)hipStreamDestroy(st);
+        if (s->check_stream) (void)hipStreamDestroy(s->check_stream);
         for (double* p : s->pinned) (void)hipHostFree(p);
         if (s->arena_base) (void)hipFree(s->arena_base);
         delete s->arena;
@@ -302,6 +306,7 @@ int destroy_impl(bqc_server* s) {
     (void)hipSetDevice(s->device);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     for (hipStream_t st : s->sides) (void)hipStreamDestroy(st);
+    (void)hipStreamDestroy(s->check_stream);
     for (double* p : s->pinned) (void)hipHostFree(p);
     (void)hipFree(s->arena_base);
     (void)hipSetDevice(prev);
@@ -316,15 +321,23 @@ int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7],
     if (!s || !ticket) return fail(BQC_EINVAL, "null argument");
     int rc = validate(o, v, src[0], src[1], src[2], src[3], src[4], src[5], src[6], !dev_in);
     if (rc != BQC_OK) return rc;
-    if (dev_in) {  // orbital energies are checked from a host copy
+    if (dev_in) {  // orbital energies are checked from a host copy, read on the server's own stream
         std::vector<double> eo(o), ev(v);
-        int prev = 0;
-        BQC_HIP(hipGetDevice(&prev));
-        BQC_HIP(hipSetDevice(s->device));
-        hipError_t e1 = hipMemcpy(eo.data(), src[0], o * sizeof(double), hipMemcpyDeviceToHost);
-        hipError_t e2 = hipMemcpy(ev.data(), src[1], v * sizeof(double), hipMemcpyDeviceToHost);
-        (void)hipSetDevice(prev);
-        if (e1 != hipSuccess || e2 != hipSuccess) return fail(BQC_EINVAL, "orbital energies are not readable device memory");
+        hipError_t err = hipSuccess;
+        {
+            std::lock_guard<std::mutex> lk(s->check_mu);
+            int prev = 0;
+            BQC_HIP(hipGetDevice(&prev));
+            BQC_HIP(hipSetDevice(s->device));
+            err = hipMemcpyAsync(eo.data(), src[0], o * sizeof(double), hipMemcpyDeviceToHost, s->check_stream);
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(ev.data(), src[1], v * sizeof(double), hipMemcpyDeviceToHost, s->check_stream);
+            if (err == hipSuccess) err = hipStreamSynchronize(s->check_stream);
+            (void)hipSetDevice(prev);
+        }
+        if (err != hipSuccess)
+            return fail(BQC_EINVAL, std::string("orbital energies are not readable device memory: ") +
+                                        hipGetErrorString(err));
         rc = validate(o, v, eo.data(), ev.data(), src[2], src[3], src[4], src[5], src[6], true);
         if (rc != BQC_OK) return rc;
     }

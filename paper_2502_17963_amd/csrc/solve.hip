@@ -131,7 +131,9 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     hipEvent_t freed[2] = {make_event(false), make_event(false)};
     // Graph mode: the whole batch sequence (both streams) is captured from
     // `st` into one graph and launched as a unit.
-    if (graph) BQC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    // Relaxed capture: other threads (submitters, other slots) keep calling the
+    // runtime while this stream is being captured.
+    if (graph) BQC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
     hipEvent_t ready = make_event(false);
     BQC_HIP(hipEventRecord(ready, st));
     BQC_HIP(hipStreamWaitEvent(side, ready, 0));  // tables and operands are in place
