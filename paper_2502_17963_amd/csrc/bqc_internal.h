@@ -31,6 +31,16 @@ struct Error : std::runtime_error {
 // EPI_T^3 tiles under the six permutations of (a, b, c).
 constexpr int EPI_T = 8;
 
+// The H buffers are stored in EPI_T^3 blocks, so that the epilogue reads every
+// block it needs as one contiguous run: with nt = ceil(v / EPI_T), element
+// (y, u, w) of one pair lies at
+//   ((y / 8 * nt + u / 8) * nt + w / 8) * 512 + (y % 8 * 8 + u % 8) * 8 + w % 8.
+// Elements with an index >= v are never written and never read.
+__host__ __device__ inline int64_t hpair_elems(int v) {
+    const int64_t nt = (v + EPI_T - 1) / EPI_T;
+    return nt * nt * nt * EPI_T * EPI_T * EPI_T;
+}
+
 inline int64_t num_triples(int o) {
     return o < 1 ? 0 : (int64_t)o * (o + 1) * (o + 2) / 6 - o;
 }
@@ -88,7 +98,7 @@ struct GemmLaunch {
     int ntrip;             // triples in the batch
     const int4* trip;      // (i, j, k, m) per triple in the batch
     Operands ops;
-    void* hbuf;            // [ntrip][3][v][v][v] in the H precision
+    void* hbuf;            // [ntrip][3] pairs of hpair_elems(v) blocked elements in the H precision
 };
 
 struct EpiLaunch {

@@ -38,6 +38,15 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
+// x if keep, else +0.  The mask is made opaque to the compiler so that the
+// load producing x stays unconditional (a plain select would be turned into a
+// branch around the load, which serialises the loads of a work group).
+__device__ __forceinline__ double keep_if(double x, bool keep) {
+    long long m = keep ? -1ll : 0ll;
+    asm volatile("" : "+v"(m));
+    return __longlong_as_double(__double_as_longlong(x) & m);
+}
+
 template <typename HT>
 __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     const int orb = blockIdx.x, t = blockIdx.y;
@@ -45,10 +54,13 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     const int4 tr = e.trip[t];
     const int i = tr.x, j = tr.y, k = tr.z;
     const int v = e.v;
-    const int64_t v2 = (int64_t)v * v, v3 = v2 * v;
-    const HT* Ha = (const HT*)e.hbuf + (int64_t)(t * 3 + 0) * v3;
-    const HT* Hb = Ha + v3;
-    const HT* Hc = Hb + v3;
+    const int nt = ceil_div(v, EPI_T);
+    const int64_t hp = hpair_elems(v);
+    const HT* Ha = (const HT*)e.hbuf + (int64_t)(t * 3 + 0) * hp;
+    const HT* Hb = Ha + hp;
+    const HT* Hc = Hb + hp;
+    // first element of block (X, Y, Z) of a blocked H buffer
+    auto blk = [&](const HT* H, int X, int Y, int Z) { return H + (((int64_t)X * nt + Y) * nt + Z) * E_T3; };
     const int64_t ov = (int64_t)e.o * v;
 
     constexpr int T = EPI_T, T2 = EPI_T * EPI_T;
@@ -64,47 +76,67 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     // tile permutations as tile ids: 0 (A,B,C) 1 (A,C,B) 2 (B,A,C) 3 (B,C,A) 4 (C,A,B) 5 (C,B,A)
     const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
-    // phase 0: singles-term factors
+    // Phases 0 and 1 issue every global load of the work group before the
+    // first LDS store, so that the group waits for one memory latency, not
+    // one per loop trip.
+    // phase 0 loads: singles-term factors (27 8x8 blocks of (ov|ov)) and t1
+    constexpr int NG = (27 * T2 + E_THREADS - 1) / E_THREADS;
     const int occ[3] = {i, j, k};
-    for (int el = threadIdx.x; el < 3 * 9 * T2; el += E_THREADS) {
+    double gv[NG];
+#pragma unroll
+    for (int n = 0; n < NG; ++n) {
+        const int el = threadIdx.x + n * E_THREADS;
         const int m = el / (9 * T2), rem = el % (9 * T2);
         const int X = rem / (3 * T2), Y = (rem / T2) % 3, xy = rem % T2;
-        const int x = TT[X] * T + xy / T, y = TT[Y] * T + xy % T;
+        const int tx = X == 0 ? TT[0] : X == 1 ? TT[1] : TT[2];
+        const int ty = Y == 0 ? TT[0] : Y == 1 ? TT[1] : TT[2];
+        const int x = tx * T + xy / T, y = ty * T + xy % T;
         // m = 0: (jb|kc) with b in X, c in Y; 1: (ia|kc); 2: (ia|jb)
         const int p = m == 0 ? j : i, q = m == 2 ? j : k;
-        double g = 0.0;
-        if (x < v && y < v) g = e.ovov[((int64_t)p * v + x) * ov + (int64_t)q * v + y];
-        Gs[m][X][Y][xy] = g;
+        // unconditional load at a clamped (valid) index, then masked: no branch
+        const double g = e.ovov[((int64_t)p * v + min(x, v - 1)) * ov + (int64_t)q * v + min(y, v - 1)];
+        gv[n] = keep_if(g, el < 27 * T2 && x < v && y < v);
     }
-    for (int el = threadIdx.x; el < 3 * 3 * T; el += E_THREADS) {
-        const int n = el / (3 * T), X = (el / T) % 3, x = TT[X] * T + el % T;
-        t1s[n][X][el % T] = x < v ? e.t1[(int64_t)occ[n] * v + x] : 0.0;
+    double t1v = 0.0;
+    if (threadIdx.x < 9 * T) {
+        const int n = threadIdx.x / (3 * T), X = (threadIdx.x / T) % 3;
+        const int tx = X == 0 ? TT[0] : X == 1 ? TT[1] : TT[2];
+        const int x = tx * T + threadIdx.x % T;
+        const int on = n == 0 ? i : n == 1 ? j : k;
+        if (x < v) t1v = e.t1[(int64_t)on * v + x];
     }
-
-    // phase 1: z-fastest threads read H_a and H_b (contiguous in c)
+    // phase 1 loads: the H_a, H_b and H_c blocks of the six tile permutations.
+    // Each block is one contiguous run of 512 elements; a wave covers 64
+    // consecutive elements of a block (one run, or eight 32-byte pieces).
+    constexpr int NE = E_T3 / E_THREADS;
+    double wv[6][NE];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
+        const int X = TT[perm[s][0]], Y = TT[perm[s][1]], Z = TT[perm[s][2]];
+        const HT* ba = blk(Ha, X, Y, Z);
+        const HT* bb = blk(Hb, Y, X, Z);
+        const HT* bc = blk(Hc, Z, X, Y);
+#pragma unroll
+        for (int n = 0; n < NE; ++n) {
+            const int el = threadIdx.x + n * E_THREADS;
             const int x = el / T2, y = (el / T) % T, z = el % T;
-            const int a = TT[perm[s][0]] * T + x, b = TT[perm[s][1]] * T + y, c = TT[perm[s][2]] * T + z;
-            double w = 0.0;
-            if (a < v && b < v && c < v)
-                w = (double)Ha[(int64_t)a * v2 + (int64_t)b * v + c] +
-                    (double)Hb[(int64_t)b * v2 + (int64_t)a * v + c];
-            Ws[s][el] = w;
+            // every element of a block is allocated; those with an index >= v
+            // were never written and are masked after an unconditional load
+            const double w = (double)ba[el] + (double)bb[(y * T + x) * T + z] + (double)bc[(z * T + x) * T + y];
+            wv[s][n] = keep_if(w, X * T + x < v && Y * T + y < v && Z * T + z < v);
         }
     }
-    __syncthreads();
-    // phase 2: b-fastest threads read H_c[c][a][b] (contiguous in b)
+    // LDS stores
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        for (int el = threadIdx.x; el < E_T3; el += E_THREADS) {
-            const int x = el / T2, z = (el / T) % T, y = el % T;
-            const int a = TT[perm[s][0]] * T + x, b = TT[perm[s][1]] * T + y, c = TT[perm[s][2]] * T + z;
-            if (a < v && b < v && c < v)
-                Ws[s][(x * T + y) * T + z] += (double)Hc[(int64_t)c * v2 + (int64_t)a * v + b];
-        }
+    for (int n = 0; n < NG; ++n) {
+        const int el = threadIdx.x + n * E_THREADS;
+        if (el < 27 * T2) (&Gs[0][0][0][0])[el] = gv[n];
     }
+    if (threadIdx.x < 9 * T) (&t1s[0][0][0])[threadIdx.x] = t1v;
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+        for (int n = 0; n < NE; ++n) Ws[s][threadIdx.x + n * E_THREADS] = wv[s][n];
     __syncthreads();
 
     // phase 3: one element (a, b, c) of the base tile and its six permutations
@@ -157,7 +189,20 @@ constexpr int R_THREADS = 256;
 __device__ double block_sum_fixed(const double* x, int64_t n) {
     __shared__ double ss[R_THREADS], cs[R_THREADS];
     double s = 0.0, c = 0.0;
-    for (int64_t idx = threadIdx.x; idx < n; idx += R_THREADS) neu_add(s, c, x[idx]);
+    // thread t adds x[t], x[t + R], x[t + 2R], ... in this order; the loads of
+    // RU consecutive terms are issued together (terms past n read x[n - 1]
+    // and are masked to +0, which leaves (s, c) unchanged)
+    constexpr int RU = 8;
+    for (int64_t idx = threadIdx.x; idx < n; idx += RU * R_THREADS) {
+        double xv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t q = idx + (int64_t)u * R_THREADS;
+            xv[u] = keep_if(x[q < n ? q : n - 1], q < n);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) neu_add(s, c, xv[u]);
+    }
     ss[threadIdx.x] = s;
     cs[threadIdx.x] = c;
     __syncthreads();

@@ -380,19 +380,22 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
         __syncthreads();
     }
 
-    const int64_t v2 = (int64_t)v * v;
-    HT* out = (HT*)g.hbuf + ((int64_t)(t * 3 + h) * v + y) * v2;
+    // H in EPI_T^3 blocks (layout in bqc_internal.h)
+    const int nt = ceil_div(v, EPI_T);
+    HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(v) +
+              (int64_t)(y >> 3) * nt * nt * 512 + (y & 7) * 64;
     const int u00 = (ub + wub) * 16, w00 = (wb + wwb) * 16;
 #pragma unroll
     for (int m = 0; m < WB; ++m)
 #pragma unroll
         for (int nn = 0; nn < WB; ++nn)
             if (m < wun && nn < wwn) {
+                const int w = w00 + nn * 16 + fr;
+                const int wo = (w >> 3) * 512 + (w & 7);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int u = u00 + m * 16 + M::row(lane, r);
-                    const int w = w00 + nn * 16 + fr;
-                    if (u < v && w < v) out[(int64_t)u * v + w] = (HT)acc[m][nn][r];
+                    if (u < v && w < v) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
                 }
             }
 }

@@ -29,13 +29,13 @@ Layout layout(int o, int v, int precision) {
     const int nt = ceil_div(v, EPI_T);
     const int64_t norbit = num_tile_orbits(nt);
     const int64_t ntrip = num_triples(o);
-    const int64_t v3 = (int64_t)v * v * v;
+    const int64_t hp = hpair_elems(v);
     Layout L;
     size_t off = 0;
     L.ops = off; off += align256(prepare_bytes(precision, o, v));
     L.trip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(int4));
     L.orbits = off; off += align256((size_t)norbit * sizeof(int4));
-    L.hbuf = off; off += 2 * align256((size_t)nb * 3 * v3 * hbuf_bytes(precision));
+    L.hbuf = off; off += 2 * align256((size_t)nb * 3 * hp * hbuf_bytes(precision));
     L.partial = off; off += align256((size_t)nb * norbit * sizeof(double));
     L.etrip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(double));
     L.energy = off; off += 256;
@@ -46,7 +46,7 @@ Layout layout(int o, int v, int precision) {
 }  // namespace
 
 int batch_triples(int o, int v, int precision) {
-    const int64_t per = 3 * (int64_t)v * v * v * hbuf_bytes(precision);
+    const int64_t per = 3 * hpair_elems(v) * hbuf_bytes(precision);
     int64_t nb = kHBudget / std::max<int64_t>(per, 1);
     nb = std::max<int64_t>(nb, 1);
     nb = std::min<int64_t>(nb, std::max<int64_t>(num_triples(o), 1));
@@ -92,7 +92,7 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     char* base = (char*)ws;
     int4* d_trip = (int4*)(base + L.trip);
     int4* d_orb = (int4*)(base + L.orbits);
-    const size_t hsize = (size_t)plan.nb * 3 * v * v * v * hbuf_bytes(prec);
+    const size_t hsize = (size_t)plan.nb * 3 * hpair_elems(v) * hbuf_bytes(prec);
     void* hbuf[2] = {base + L.hbuf, base + L.hbuf + align256(hsize)};
     double* partial = (double*)(base + L.partial);
     double* etrip = (double*)(base + L.etrip);
