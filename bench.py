@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "(T) TFLOP/s at |ΔE_T|≤1 µEh vs FP64; fragment req/s + p50/p99 latency"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp8": 5000.0}
+MFMA_PER_FLOP = {"fp64": 1, "fp32": 1, "bf16x3": 3, "fp8": 1}
 MIXED_REL_GATE = 1e-6
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
 
@@ -50,6 +51,11 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=100.0, help="serving arena size")
     ap.add_argument("--input-cap-gb", type=float, default=80.0,
                     help="serving: device memory allowed for generated-but-unfinished fragment inputs")
+    ap.add_argument("--shares", type=int, default=0,
+                    help="run each solve as this many consecutive shares of the unique triples, "
+                         "with a progress line after each (0: 1, or 16 for the largest fragment)")
+    ap.add_argument("--device-inputs", type=int, default=-1,
+                    help="1: generate the inputs on the GPU (-1: only for the largest fragment)")
     ap.add_argument("--rate-frac", type=float, default=0.7,
                     help="serving open loop: arrival rate as a fraction of the closed-loop req/s (0: skip)")
     return ap.parse_args()
@@ -183,10 +189,13 @@ def run_serving(args):
         rec, span, kept = _serve_stream(bqc, srv, shapes, [0.0] * len(shapes), cap, keep_idx)
         closed_rps = len(shapes) / span
         lat = np.array([rec[i]["latency_s"] for i in range(len(shapes))])
+        qw = np.array([rec[i]["queue_s"] for i in range(len(shapes))])
         out["closed_loop"] = {"req_s": round(closed_rps, 4), "makespan_s": round(span, 2),
                               "tflops": round(F.sum() / span / 1e12, 2),
                               "p50_s": round(float(np.percentile(lat, 50)), 3),
-                              "p99_s": round(float(np.percentile(lat, 99)), 3)}
+                              "p99_s": round(float(np.percentile(lat, 99)), 3),
+                              "admission_wait_p50_s": round(float(np.percentile(qw, 50)), 3),
+                              "admission_wait_p99_s": round(float(np.percentile(qw, 99)), 3)}
         print(f"[serving] closed loop {len(shapes)} req in {span:.1f} s: {closed_rps:.3f} req/s, "
               f"{F.sum() / span / 1e12:.1f} TFLOP/s", file=sys.stderr, flush=True)
         # alone vs in the mix, bitwise
@@ -203,10 +212,13 @@ def run_serving(args):
             arr = [s["t_arrive"] for s in serving_stream(256, rate=rate)[:args.requests]]
             rec2, span2, _ = _serve_stream(bqc, srv, shapes, arr, cap, set())
             lat2 = np.array([rec2[i]["latency_s"] for i in range(len(shapes))])
+            qw2 = np.array([rec2[i]["queue_s"] for i in range(len(shapes))])
             out["open_loop"] = {"rate_req_s": round(rate, 4), "req_s": round(len(shapes) / span2, 4),
                                 "makespan_s": round(span2, 2),
                                 "p50_s": round(float(np.percentile(lat2, 50)), 3),
                                 "p99_s": round(float(np.percentile(lat2, 99)), 3),
+                                "admission_wait_p50_s": round(float(np.percentile(qw2, 50)), 3),
+                                "admission_wait_p99_s": round(float(np.percentile(qw2, 99)), 3),
                                 "tflops": round(F.sum() / span2 / 1e12, 2)}
             print(f"[serving] open loop at {rate:.3f} req/s: p50 {out['open_loop']['p50_s']} s "
                   f"p99 {out['open_loop']['p99_s']} s", file=sys.stderr, flush=True)
@@ -249,24 +261,57 @@ def main():
     from synth import CONFIGS, flops_alg, make_inputs
 
     o, v, naux, seed = CONFIGS[args.workload]
+    big = args.workload == "largest_fragment"
+    on_device = args.device_inputs == 1 or (args.device_inputs == -1 and big)
+    shares = args.shares if args.shares > 0 else (16 if big else 1)
     t_gen = time.perf_counter()
-    x = make_inputs(o, v, naux, seed)
-    gen_s = time.perf_counter() - t_gen
-    dev = [torch.from_numpy(a).to("cuda:0") for a in x.arrays()]
+    if on_device:
+        # the 42 GB FP64 (ia|bc) of the largest fragment is generated on the GPU
+        from synth import make_inputs_device
+        x = None
+        dev = make_inputs_device(o, v, naux, seed)
+        nbytes = sum(a.numel() * 8 for a in dev)
+        args.no_cpu = True  # the oracle sample needs host inputs
+    else:
+        x = make_inputs(o, v, naux, seed)
+        dev = [torch.from_numpy(a).to("cuda:0") for a in x.arrays()]
+        nbytes = x.nbytes()
     torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t_gen
     F = flops_alg(o, v)
     bqc.lib()
+    ntrip = bqc.num_triples(o)
+    cuts = [round(ntrip * q / shares) for q in range(shares + 1)]
     print(f"[bench] workload {args.workload} o={o} v={v} naux={naux} F_alg={F:.3e} "
-          f"inputs {x.nbytes() / 1e9:.2f} GB generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+          f"inputs {nbytes / 1e9:.2f} GB generated {'on the GPU' if on_device else 'on the host'} "
+          f"in {gen_s:.1f} s; {shares} share(s) per solve", file=sys.stderr, flush=True)
+
+    def solve(prec, timing=True):
+        """One solve as `shares` consecutive triple shares; E_T is their
+        fixed-order sum and the stats are summed over the shares."""
+        if shares == 1:
+            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=timing, stats=True)
+            return e, ex["stats"]
+        tot, agg, t0 = 0.0, None, time.perf_counter()
+        for q, (b, e_) in enumerate(zip(cuts[:-1], cuts[1:])):
+            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=timing, stats=True, triple_range=(b, e_))
+            tot += e
+            st = ex["stats"]
+            agg = dict(st) if agg is None else {k: (agg[k] + st[k] if k in ("gemm_s", "epilogue_s", "gemm_launches",
+                                                                              "epilogue_launches", "prepare_s", "gpu_s",
+                                                                              "flops", "n_triples") else st[k])
+                                                for k in st}
+            print(f"[bench] {prec} share {q + 1}/{shares} (triples {b}..{e_}) done at "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        return tot, agg
 
     results = {}
     e64 = None
     if not args.no_fp64:
         t0 = time.perf_counter()
-        e64, ex = bqc.t_energy(o, v, *dev, precision="fp64", timing=True)
+        e64, st = solve("fp64")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        st = ex["stats"]
         results["fp64"] = {"E_T": e64, "s": dt, "tflops": F / dt / 1e12, "stats": st}
         print(f"[bench] fp64 E_T={e64:.12e} {dt:.2f} s {F / dt / 1e12:.2f} TFLOP/s "
               f"gemm {st['gemm_s']:.2f} s / {st['gemm_launches']} launches, epilogue {st['epilogue_s']:.2f} s",
@@ -275,14 +320,14 @@ def main():
     head = None
     for prec in [p.strip() for p in args.precisions.split(",") if p.strip()]:
         for _ in range(args.warmup):
-            bqc.t_energy(o, v, *dev, precision=prec)
+            solve(prec, timing=False)
         torch.cuda.synchronize()
         energies, stats = [], []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=True)
+            e, st = solve(prec)
             energies.append(e)
-            stats.append(ex["stats"])
+            stats.append(st)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / max(args.steps, 1)
         e = energies[-1]
@@ -291,6 +336,7 @@ def main():
         gemm_n = sum(s["gemm_launches"] for s in stats)
         epi_s = sum(s["epilogue_s"] for s in stats)
         rec = {"E_T": e, "s": dt, "tflops": F / dt / 1e12, "rel_vs_fp64": rel,
+               "prepare_s": sum(s["prepare_s"] for s in stats) / max(len(stats), 1),
                "dE_uEh_vs_fp64": abs(e - e64) * 1e6 if e64 is not None else None,
                "gemm_avg_s": gemm_s / max(gemm_n, 1), "gemm_launches_per_step": gemm_n / max(args.steps, 1),
                "gemm_frac": gemm_s / (dt * args.steps), "epilogue_frac": epi_s / (dt * args.steps),
@@ -326,8 +372,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp8": "fp8"}[head],
-        "data": "synthetic (seeded DF factors, MP1 t2, random t1)",
-        "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": naux, "seed": seed,
+        "data": "synthetic (seeded DF factors, MP1 t2, random t1)" + ("; generated on the GPU" if on_device else ""),
+        "config": {"workload": args.workload, "shares_per_solve": shares, "nocc": o, "nvir": v, "naux": naux, "seed": seed,
                    "precision": head, "parallelism": "single-GPU"},
         "E_T": hr["E_T"],
         "E_T_fp64": e64,
@@ -337,7 +383,10 @@ def main():
         "precisions": {k: {kk: vv for kk, vv in r.items() if kk != "stats"} for k, r in results.items()},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": "h_gemm_kernel", "flops_per_launch": flops_launch},
+                     "kernel": "h_gemm_kernel", "flops_per_launch": flops_launch,
+                     # split-BF16x3 issues three BF16 MFMA products per algorithmic product
+                     "mfma_products_per_flop": MFMA_PER_FLOP[head],
+                     "mfma_pipe_frac": round(achieved * MFMA_PER_FLOP[head] / peak, 4)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)

@@ -78,7 +78,17 @@ typedef struct {
     int32_t timing;           /* 1: record per-kernel HIP events and fill the kernel fields of stats */
     void*   stream;           /* hipStream_t to run on, or NULL for the library's stream of `device` */
     double* triple_energies;  /* NULL, or a HOST array of bqc_t_num_triples(nocc) doubles that receives
-                                 the per-triple energies e_ijk in unique-triple order */
+                                 the per-triple energies e_ijk in unique-triple order (with a triple
+                                 range, only the entries of the range are written) */
+    int64_t triple_begin;     /* first unique triple of the share (see triple_end) */
+    int64_t triple_end;       /* Share of the solve: only the unique triples with index in
+                                 [triple_begin, triple_end) of the unique-triple order (i <= j <= k,
+                                 lexicographic, i = j = k skipped) are computed, and E_T is their
+                                 fixed-order compensated sum.  triple_end = 0 means all triples
+                                 (triple_begin must then be 0).  Otherwise 0 <= triple_begin <
+                                 triple_end <= bqc_t_num_triples(nocc), else BQC_EINVAL.  Shares of
+                                 one solve (one per GPU, or consecutive pieces of a long solve) add
+                                 up to the whole: every triple's energy does not depend on the range. */
 } bqc_t_opts;
 
 /* Per-solve measurements.  Times are seconds. */

@@ -28,7 +28,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class TOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("inputs_on_device", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("triple_energies", _dp)]
+                ("stream", ctypes.c_void_p), ("triple_energies", _dp),
+                ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64)]
 
 
 class TStats(ctypes.Structure):
@@ -151,11 +152,14 @@ def _ptrs(arrays):
 
 
 def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64",
-             device=0, triple_energies=False, timing=False, stream=None, stats=False):
+             device=0, triple_energies=False, timing=False, stream=None, stats=False,
+             triple_range=None):
     """E_T through bqc_t_energy_ex.
 
+    triple_range=(begin, end) solves only that share of the unique triples.
     Returns E_T, or (E_T, extras) when triple_energies or stats is requested;
-    extras holds "triples" (numpy array in unique-triple order) and/or "stats".
+    extras holds "triples" (numpy array in unique-triple order; with a range,
+    entries outside it are zero) and/or "stats".
     """
     arrays = (eps_o, eps_v, t1, t2, ovvv, ooov, ovov)
     ptrs, on_dev, keep = _ptrs(arrays)
@@ -164,6 +168,8 @@ def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64
     opts.device = device
     opts.inputs_on_device = 1 if on_dev else 0
     opts.timing = 1 if timing else 0
+    if triple_range is not None:
+        opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
     if stream is not None:
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:

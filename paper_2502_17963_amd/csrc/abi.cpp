@@ -107,6 +107,10 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     const bool dev_in = op.inputs_on_device != 0;
     int rc = validate(o, v, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, !dev_in);
     if (rc != BQC_OK) return rc;
+    const int64_t ntrip_all = num_triples(o);
+    if (op.triple_end == 0 ? op.triple_begin != 0
+                           : (op.triple_begin < 0 || op.triple_begin >= op.triple_end || op.triple_end > ntrip_all))
+        return fail(BQC_EINVAL, "triple range outside [0, bqc_t_num_triples(nocc)] or empty");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BQC_EDEVICE, "no HIP device");
     if (op.device < 0 || op.device >= ndev) return fail(BQC_EINVAL, "device ordinal out of range");
@@ -158,23 +162,25 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
     }
 
-    const Plan plan = make_plan(o, v, op.precision);
+    const Plan plan = make_plan(o, v, op.precision, op.triple_begin, op.triple_end);
+    const int64_t nshare = plan.end - plan.begin;
     ensure(ctx->ws, ctx->ws_size, (size_t)workspace_bytes(o, v, op.precision));
     SolveStats ss;
     enqueue_solve(plan, in, ctx->ws, nullptr, st, ctx->side, op.timing != 0, stats ? &ss : nullptr);
     BQC_HIP(hipMemcpyAsync(ctx->host_energy, workspace_energy(ctx->ws, o, v, op.precision), sizeof(double),
                            hipMemcpyDeviceToHost, st));
     std::vector<double> etrip;
-    if (op.triple_energies && ntrip > 0) {
-        etrip.resize(ntrip);
-        BQC_HIP(hipMemcpyAsync(etrip.data(), workspace_etrip(ctx->ws, o, v, op.precision),
-                               ntrip * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (op.triple_energies && nshare > 0) {
+        etrip.resize(nshare);
+        BQC_HIP(hipMemcpyAsync(etrip.data(), workspace_etrip(ctx->ws, o, v, op.precision) + plan.begin,
+                               nshare * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     BQC_HIP(hipStreamSynchronize(st));
     const double e = *ctx->host_energy;
     if (!std::isfinite(e)) return fail(BQC_EDEVICE, "non-finite energy (device arithmetic failed)");
     *E_T = e;
-    if (op.triple_energies && ntrip > 0) std::memcpy(op.triple_energies, etrip.data(), ntrip * sizeof(double));
+    if (op.triple_energies && nshare > 0)
+        std::memcpy(op.triple_energies + plan.begin, etrip.data(), nshare * sizeof(double));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->upload_s = upload_s;
@@ -185,9 +191,9 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         stats->gemm_launches = ss.gemm_launches;
         stats->epilogue_launches = ss.epi_launches;
         stats->footprint_bytes = ss.footprint + (dev_in ? 0 : (uint64_t)input_bytes(o, v));
-        stats->flops = 12.0 * (double)ntrip * (double)v * v * v * (double)(v + o);
+        stats->flops = 12.0 * (double)nshare * (double)v * v * v * (double)(v + o);
         stats->precision = op.precision;
-        stats->n_triples = (int32_t)ntrip;
+        stats->n_triples = (int32_t)nshare;
         stats->total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
     }
     return BQC_OK;

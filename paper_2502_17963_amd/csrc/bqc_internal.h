@@ -154,8 +154,10 @@ struct Plan {
     int o = 0, v = 0, precision = 0, nb = 0;
     std::vector<int4> trip;    // unique triples (i, j, k, m)
     std::vector<int4> orbits;  // epilogue tile orbits
+    int64_t begin = 0, end = 0;  // the solved share [begin, end) of `trip`
 };
-Plan make_plan(int o, int v, int precision);
+// Plan of the share [begin, end) of the unique triples (end = 0: all).
+Plan make_plan(int o, int v, int precision, int64_t begin = 0, int64_t end = 0);
 
 // A solve whose inputs are resident on the device.  The caller owns `ws`
 // (workspace_bytes(o, v, precision) bytes, 256-byte aligned) and the stream.

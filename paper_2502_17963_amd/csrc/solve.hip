@@ -62,7 +62,7 @@ int64_t input_bytes(int o, int v) {
     return n * 8 + 7 * 256;
 }
 
-Plan make_plan(int o, int v, int precision) {
+Plan make_plan(int o, int v, int precision, int64_t begin, int64_t end) {
     Plan p;
     p.o = o;
     p.v = v;
@@ -75,6 +75,8 @@ Plan make_plan(int o, int v, int precision) {
                 const int m = (i < j && j < k) ? 6 : 3;
                 p.trip.push_back(make_int4(i, j, k, m));
             }
+    p.begin = end > 0 ? begin : 0;
+    p.end = end > 0 ? end : (int64_t)p.trip.size();
     const int nt = ceil_div(v, EPI_T);
     for (int A = 0; A < nt; ++A)
         for (int B = 0; B <= A; ++B)
@@ -140,8 +142,9 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
 
     std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm_ev, epi_ev;
     int batch = 0;
-    for (int b0 = 0; b0 < ntrip; b0 += plan.nb, ++batch) {
-        const int nb = std::min(plan.nb, ntrip - b0);
+    const int t_begin = (int)plan.begin, t_end = (int)plan.end;
+    for (int b0 = t_begin; b0 < t_end; b0 += plan.nb, ++batch) {
+        const int nb = std::min(plan.nb, t_end - b0);
         const int k = batch & 1;
         if (batch >= 2) BQC_HIP(hipStreamWaitEvent(st, freed[k], 0));
         GemmLaunch g;
@@ -167,7 +170,7 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     hipEvent_t done_side = make_event(false);
     BQC_HIP(hipEventRecord(done_side, side));
     BQC_HIP(hipStreamWaitEvent(st, done_side, 0));
-    launch_reduce_total(etrip, ntrip, (double*)(base + L.energy), st);
+    launch_reduce_total(etrip + t_begin, t_end - t_begin, (double*)(base + L.energy), st);
     if (graph) {
         hipGraph_t gr = nullptr;
         BQC_HIP(hipStreamEndCapture(st, &gr));

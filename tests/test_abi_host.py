@@ -39,11 +39,12 @@ def test_footprint_grows_with_size_and_shrinks_with_precision():
     assert f32 > 0
 
 
-def _call(o, v, arrays, E=True, precision=0):
+def _call(o, v, arrays, E=True, precision=0, triple_range=(0, 0)):
     ptrs = [None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrays]
     e = ctypes.c_double(123.0)
     opts = binding.TOpts()
     opts.precision = precision
+    opts.triple_begin, opts.triple_end = triple_range
     rc = bqc.lib().bqc_t_energy_ex(o, v, *ptrs, ctypes.byref(opts), ctypes.byref(e) if E else None, None)
     return rc, e.value
 
@@ -61,6 +62,17 @@ def test_invalid_sizes_and_pointers():
     assert _call(3, 5, arr, E=False)[0] == binding.EINVAL
     assert _call(3, 5, arr, precision=7)[0] == binding.EINVAL
     assert "precision" in bqc.last_error()
+
+
+def test_triple_range_checks():
+    # o = 4: 16 unique triples; a share is [begin, end) with 0 <= begin < end <= 16
+    x = make_inputs(4, 6, 12, 0)
+    arr = list(x.arrays())
+    assert bqc.num_triples(4) == 16
+    for rng in [(1, 0), (-1, 3), (3, 3), (5, 2), (0, 17), (16, 17)]:
+        rc, e = _call(4, 6, arr, triple_range=rng)
+        assert rc == binding.EINVAL and e == 123.0, rng
+        assert "triple range" in bqc.last_error()
 
 
 def test_gap_and_finiteness_checks():

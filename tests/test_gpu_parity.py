@@ -166,3 +166,29 @@ def test_small_and_ragged_fp8():
               flush=True)
         assert np.isfinite(e)
         assert abs(e - ref) <= 1e-2 * abs(ref), (o, v, e, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_triple_shares_add_up_to_the_solve(prec):
+    """Consecutive shares [begin, end) of the unique triples: each triple's
+    energy is bitwise the one of the whole solve, and the shares' energies sum
+    to E_T (different summation grouping only)."""
+    import torch
+    bqc = _bqc()
+    o, v, naux, seed = 6, 30, 120, 0
+    print(f"case triple shares {prec} o={o} v={v}", flush=True)
+    x = make_inputs(o, v, naux, seed)
+    dev = [torch.from_numpy(a).to("cuda:0") for a in x.arrays()]
+    e_all, ex = bqc.t_energy(o, v, *dev, precision=prec, triple_energies=True)
+    torch.cuda.synchronize()
+    n = bqc.num_triples(o)
+    cuts = [0, 1, n // 3, n - 1, n]
+    parts = []
+    for b, e in zip(cuts[:-1], cuts[1:]):
+        es, exs = bqc.t_energy(o, v, *dev, precision=prec, triple_energies=True, triple_range=(b, e))
+        torch.cuda.synchronize()
+        assert np.array_equal(exs["triples"][b:e], ex["triples"][b:e])
+        assert np.all(exs["triples"][:b] == 0) and np.all(exs["triples"][e:] == 0)
+        assert abs(es - float(np.sum(ex["triples"][b:e]))) <= 1e-14 * max(abs(es), 1e-300)
+        parts.append(es)
+    assert abs(sum(parts) - e_all) <= 1e-13 * abs(e_all)
