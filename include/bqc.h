@@ -141,8 +141,9 @@ typedef struct {
     int32_t  precision;        /* bqc_precision for every request */
     uint64_t mem_budget_bytes; /* 0: 85% of the device's free memory at creation */
     int32_t  max_inflight;     /* 0: 4 */
-    int32_t  direct_launch;    /* 0: each request's triple-batch launch sequence is captured into one
-                                  hipGraph and launched as a unit; 1: kernels are launched one by one */
+    int32_t  direct_launch;    /* 0: each request's triple-batch launch sequence is built as one hipGraph
+                                  (kernel nodes, no stream capture) and launched as a unit; 1: kernels
+                                  are launched one by one on the slot's two streams */
 } bqc_server_cfg;
 
 /* Creates a server; *out is written on BQC_OK. */

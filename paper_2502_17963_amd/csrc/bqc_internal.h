@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -123,16 +124,61 @@ struct Sizes {
 Sizes factor_sizes(int o, int v, int precision);
 
 // ------------------------------------------------------------------ launchers
+// One kernel launch held as data (function, shape, argument values), so that
+// it can be launched on a stream or added to a hipGraph as a kernel node.
+struct KernelCall {
+    const void* fn = nullptr;
+    dim3 grid, block;
+    unsigned shmem = 0;
+    alignas(16) char buf[384];
+    size_t at[8] = {};
+    int nargs = 0;
+    size_t used = 0;
+    template <class T>
+    KernelCall& arg(const T& x) {
+        used = (used + alignof(T) - 1) / alignof(T) * alignof(T);
+        if (nargs >= 8 || used + sizeof(T) > sizeof(buf)) throw Error(-1, "kernel argument buffer too small");
+        std::memcpy(buf + used, &x, sizeof(T));
+        at[nargs++] = used;
+        used += sizeof(T);
+        return *this;
+    }
+    // argument pointers into this object's buffer (valid while it lives)
+    void pointers(void** p) const {
+        for (int a = 0; a < nargs; ++a) p[a] = (void*)(buf + at[a]);
+    }
+    void launch(hipStream_t st) const {
+        void* p[8];
+        pointers(p);
+        BQC_HIP(hipLaunchKernel(fn, grid, block, p, shmem, st));
+    }
+    // kernel node after `deps` (the node copies the argument values)
+    hipGraphNode_t add_to(hipGraph_t gr, const std::vector<hipGraphNode_t>& deps) const {
+        void* p[8];
+        pointers(p);
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void*>(fn);
+        kp.gridDim = grid;
+        kp.blockDim = block;
+        kp.sharedMemBytes = shmem;
+        kp.kernelParams = p;
+        kp.extra = nullptr;
+        hipGraphNode_t n = nullptr;
+        BQC_HIP(hipGraphAddKernelNode(&n, gr, deps.empty() ? nullptr : deps.data(), deps.size(), &kp));
+        return n;
+    }
+};
+
 void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* ops,
                     hipStream_t st);
 int64_t prepare_bytes(int precision, int o, int v);
 
-void launch_gemm(int precision, const GemmLaunch& g, hipStream_t st);
+KernelCall gemm_call(int precision, const GemmLaunch& g);
 int wave_blocks(int v);  // contraction wave tile (16-blocks per side) used for this v
-void launch_epilogue(int precision, const EpiLaunch& e, hipStream_t st);
-void launch_reduce_triples(const double* partial, int ntrip, int norbit, const int4* trip,
-                           double* e_trip, hipStream_t st);
-void launch_reduce_total(const double* e_trip, int64_t n, double* out, hipStream_t st);
+KernelCall epilogue_call(int precision, const EpiLaunch& e);
+KernelCall reduce_triples_call(const double* partial, int ntrip, int norbit, const int4* trip,
+                               double* e_trip);
+KernelCall reduce_total_call(const double* e_trip, int64_t n, double* out);
 
 // ------------------------------------------------------------------ solve
 struct SolveStats {
@@ -166,8 +212,9 @@ Plan make_plan(int o, int v, int precision, int64_t begin = 0, int64_t end = 0);
 // `side` is a second stream of the same device on which the epilogues run,
 // overlapping the contractions on `st`; everything is ordered back onto `st`.
 // Returns after `st` has drained (the solve is complete).  graph = true
-// captures the batch sequence into a hipGraph and launches it as one unit
-// (no per-kernel timing then).
+// builds the batch sequence as one hipGraph (kernel nodes with the same
+// dependencies; no stream capture, `side` unused) and launches it on `st` as
+// one unit (no per-kernel timing then).
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
                    hipStream_t st, hipStream_t side, bool timing, SolveStats* stats, bool graph = false);
 

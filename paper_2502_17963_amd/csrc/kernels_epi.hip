@@ -234,26 +234,33 @@ __global__ __launch_bounds__(R_THREADS) void reduce_total_kernel(const double* e
 
 }  // namespace
 
-void launch_epilogue(int precision, const EpiLaunch& e, hipStream_t st) {
+KernelCall epilogue_call(int precision, const EpiLaunch& e) {
     if (e.ntrip > 65535) throw Error(-1, "epilogue batch too large");
-    dim3 grid(e.norbit, e.ntrip), block(E_THREADS);
-    if (precision == 0)
-        hipLaunchKernelGGL(epilogue_kernel<double>, grid, block, 0, st, e);
-    else
-        hipLaunchKernelGGL(epilogue_kernel<float>, grid, block, 0, st, e);
-    BQC_HIP(hipGetLastError());
+    KernelCall k;
+    k.fn = precision == 0 ? (const void*)&epilogue_kernel<double> : (const void*)&epilogue_kernel<float>;
+    k.grid = dim3(e.norbit, e.ntrip);
+    k.block = dim3(E_THREADS);
+    k.arg(e);
+    return k;
 }
 
-void launch_reduce_triples(const double* partial, int ntrip, int norbit, const int4* trip,
-                           double* e_trip, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_triples_kernel, dim3(ntrip), dim3(R_THREADS), 0, st, partial, norbit,
-                       trip, e_trip);
-    BQC_HIP(hipGetLastError());
+KernelCall reduce_triples_call(const double* partial, int ntrip, int norbit, const int4* trip,
+                               double* e_trip) {
+    KernelCall k;
+    k.fn = (const void*)&reduce_triples_kernel;
+    k.grid = dim3(ntrip);
+    k.block = dim3(R_THREADS);
+    k.arg(partial).arg(norbit).arg(trip).arg(e_trip);
+    return k;
 }
 
-void launch_reduce_total(const double* e_trip, int64_t n, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_total_kernel, dim3(1), dim3(R_THREADS), 0, st, e_trip, n, out);
-    BQC_HIP(hipGetLastError());
+KernelCall reduce_total_call(const double* e_trip, int64_t n, double* out) {
+    KernelCall k;
+    k.fn = (const void*)&reduce_total_kernel;
+    k.grid = dim3(1);
+    k.block = dim3(R_THREADS);
+    k.arg(e_trip).arg(n).arg(out);
+    return k;
 }
 
 }  // namespace bqc

@@ -405,15 +405,19 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
 namespace {
 
 template <int PREC, class G>
-void launch_geo(const GemmLaunch& g, hipStream_t st) {
+KernelCall geo_call(const GemmLaunch& g) {
     const int nblk = ceil_div(g.v, 16);
     const int ntile_u = ceil_div(nblk, G::WU * G::WB), ntile_w = ceil_div(nblk, G::WW * G::WB);
     const int64_t n64 = (int64_t)g.ntrip * 3 * g.v * ntile_u * ntile_w;
     if (n64 > ((int64_t)1 << 31) - 8) throw Error(-1, "contraction grid too large");
     const int n_wg = (int)n64;
     const int per_xcd = ceil_div(n_wg, 8);
-    hipLaunchKernelGGL((h_gemm_kernel<PREC, G>), dim3(per_xcd * 8), dim3(G::NTHR), 0, st, g, n_wg, nblk,
-                       ntile_u, ntile_w, per_xcd);
+    KernelCall k;
+    k.fn = (const void*)&h_gemm_kernel<PREC, G>;
+    k.grid = dim3(per_xcd * 8);
+    k.block = dim3(G::NTHR);
+    k.arg(g).arg(n_wg).arg(nblk).arg(ntile_u).arg(ntile_w).arg(per_xcd);
+    return k;
 }
 
 // Share of the computed 16x16 block products that are useful when the nblk
@@ -425,13 +429,12 @@ double block_use(int nblk, int wb) {
 }
 
 template <int PREC>
-void launch_mode(const GemmLaunch& g, hipStream_t st) {
-    const int wb = wave_blocks(g.v);
-    switch (wb) {
-        case 2: launch_geo<PREC, Geo<2, 2, 2>>(g, st); break;
-        case 3: launch_geo<PREC, Geo<2, 2, 3>>(g, st); break;
-        case 4: launch_geo<PREC, Geo<2, 2, 4>>(g, st); break;
-        default: launch_geo<PREC, Geo<2, 2, 5>>(g, st); break;
+KernelCall mode_call(const GemmLaunch& g) {
+    switch (wave_blocks(g.v)) {
+        case 2: return geo_call<PREC, Geo<2, 2, 2>>(g);
+        case 3: return geo_call<PREC, Geo<2, 2, 3>>(g);
+        case 4: return geo_call<PREC, Geo<2, 2, 4>>(g);
+        default: return geo_call<PREC, Geo<2, 2, 5>>(g);
     }
 }
 
@@ -455,15 +458,14 @@ int wave_blocks(int v) {
 // A 320 x 160 tile with 8 waves loads a quarter fewer operand bytes per flop
 // than 160 x 160 but measured slower (FP32 7.9 s vs 7.6 s, BF16x3 3.7 s vs
 // 3.4 s per solve at o = 32, v = 300).
-void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st) {
+KernelCall gemm_call(int precision, const GemmLaunch& g) {
     switch (precision) {
-        case 0: launch_mode<0>(g, st); break;
-        case 1: launch_mode<1>(g, st); break;
-        case 2: launch_mode<2>(g, st); break;
-        case 3: launch_mode<3>(g, st); break;
+        case 0: return mode_call<0>(g);
+        case 1: return mode_call<1>(g);
+        case 2: return mode_call<2>(g);
+        case 3: return mode_call<3>(g);
         default: throw Error(-1, "unsupported precision for the MFMA contraction");
     }
-    BQC_HIP(hipGetLastError());
 }
 
 }  // namespace bqc

@@ -12,8 +12,9 @@
 //     after which admission waits for it), uploads it, enqueues its whole
 //     solve on its stream and waits for it, so that admitted requests run
 //     concurrently on the device while new ones keep arriving.  By default
-//     the request's triple-batch launch sequence is captured into one hipGraph
-//     and launched as a unit.
+//     the request's triple-batch launch sequence is built as one hipGraph
+//     (kernel nodes with the pipeline's dependencies, no stream capture) and
+//     launched as a unit.
 // A request's launch sequence is the one bqc_t_energy_ex uses, so its result
 // is bitwise identical alone and in the mix.
 #include <algorithm>
@@ -105,7 +106,7 @@ struct Request {
 
 struct bqc_server {
     int device = 0, precision = 0, max_inflight = 4;
-    bool graphs = true;  // capture each request's launch sequence into a hipGraph
+    bool graphs = true;  // run each request's launch sequence as one hipGraph
     uint64_t budget = 0;
     void* arena_base = nullptr;
     bqc::Arena* arena = nullptr;

@@ -9,10 +9,6 @@
 
 namespace bqc {
 
-void launch_gemm_fp(int precision, const GemmLaunch& g, hipStream_t st);
-
-void launch_gemm(int precision, const GemmLaunch& g, hipStream_t st) { launch_gemm_fp(precision, g, st); }
-
 namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -129,62 +125,86 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
 
     // Two H buffers: the contraction of batch b+1 (stream st, MFMA-bound)
     // overlaps the epilogue of batch b (stream side, memory-bound).
-    hipEvent_t filled[2] = {make_event(false), make_event(false)};
-    hipEvent_t freed[2] = {make_event(false), make_event(false)};
-    // Graph mode: the whole batch sequence (both streams) is captured from
-    // `st` into one graph and launched as a unit.
-    // Relaxed capture: other threads (submitters, other slots) keep calling the
-    // runtime while this stream is being captured.
-    if (graph) BQC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-    hipEvent_t ready = make_event(false);
-    BQC_HIP(hipEventRecord(ready, st));
-    BQC_HIP(hipStreamWaitEvent(side, ready, 0));  // tables and operands are in place
-
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm_ev, epi_ev;
-    int batch = 0;
     const int t_begin = (int)plan.begin, t_end = (int)plan.end;
-    for (int b0 = t_begin; b0 < t_end; b0 += plan.nb, ++batch) {
-        const int nb = std::min(plan.nb, t_end - b0);
-        const int k = batch & 1;
-        if (batch >= 2) BQC_HIP(hipStreamWaitEvent(st, freed[k], 0));
+    auto gemm_of = [&](int b0, int nb, int k) {
         GemmLaunch g;
         g.o = o; g.v = v; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf[k];
-        hipEvent_t g0 = mark(timing, st);
-        launch_gemm(prec, g, st);
-        hipEvent_t g1 = mark(timing, st);
-        if (timing) gemm_ev.emplace_back(g0, g1);
-        BQC_HIP(hipEventRecord(filled[k], st));
-
-        BQC_HIP(hipStreamWaitEvent(side, filled[k], 0));
+        return gemm_call(prec, g);
+    };
+    auto epi_of = [&](int b0, int nb, int k) {
         EpiLaunch e;
         e.o = o; e.v = v; e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf[k];
         e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
         e.orbits = d_orb; e.norbit = norbit; e.partial = partial;
-        hipEvent_t p0 = mark(timing, side);
-        launch_epilogue(prec, e, side);
-        hipEvent_t p1 = mark(timing, side);
-        if (timing) epi_ev.emplace_back(p0, p1);
-        launch_reduce_triples(partial, nb, norbit, d_trip + b0, etrip + b0, side);
-        BQC_HIP(hipEventRecord(freed[k], side));
-    }
-    hipEvent_t done_side = make_event(false);
-    BQC_HIP(hipEventRecord(done_side, side));
-    BQC_HIP(hipStreamWaitEvent(st, done_side, 0));
-    launch_reduce_total(etrip + t_begin, t_end - t_begin, (double*)(base + L.energy), st);
+        return epilogue_call(prec, e);
+    };
+    double* d_total = (double*)(base + L.energy);
+
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm_ev, epi_ev;
     if (graph) {
+        // The batch sequence as one explicitly built hipGraph: kernel nodes
+        // with the dependencies of the two-stream pipeline (no stream capture,
+        // so other threads' runtime calls cannot interfere with it):
+        //   gemm(b)   after gemm(b-1) and reduce(b-2)  (H buffer b mod 2 free)
+        //   epi(b)    after gemm(b) and reduce(b-1)
+        //   reduce(b) after epi(b);  total after every reduce and the last gemm
         hipGraph_t gr = nullptr;
-        BQC_HIP(hipStreamEndCapture(st, &gr));
-        hipGraphExec_t ex = nullptr;
-        const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
-            (void)hipGraphDestroy(gr);
-            BQC_HIP(ie);
+        BQC_HIP(hipGraphCreate(&gr, 0));
+        struct GraphGuard { hipGraph_t g; ~GraphGuard() { if (g) (void)hipGraphDestroy(g); } } gg{gr};
+        std::vector<hipGraphNode_t> red;
+        hipGraphNode_t last_gemm = nullptr;
+        int batch = 0;
+        for (int b0 = t_begin; b0 < t_end; b0 += plan.nb, ++batch) {
+            const int nb = std::min(plan.nb, t_end - b0);
+            const int k = batch & 1;
+            std::vector<hipGraphNode_t> dg;
+            if (last_gemm) dg.push_back(last_gemm);
+            if (batch >= 2) dg.push_back(red[batch - 2]);
+            last_gemm = gemm_of(b0, nb, k).add_to(gr, dg);
+            std::vector<hipGraphNode_t> de{last_gemm};
+            if (batch >= 1) de.push_back(red[batch - 1]);
+            const hipGraphNode_t ep = epi_of(b0, nb, k).add_to(gr, de);
+            red.push_back(reduce_triples_call(partial, nb, norbit, d_trip + b0, etrip + b0).add_to(gr, {ep}));
         }
+        std::vector<hipGraphNode_t> dt;
+        if (!red.empty()) dt.push_back(red.back());
+        if (last_gemm) dt.push_back(last_gemm);
+        reduce_total_call(etrip + t_begin, t_end - t_begin, d_total).add_to(gr, dt);
+        hipGraphExec_t ex = nullptr;
+        BQC_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
         const hipError_t le = hipGraphLaunch(ex, st);
         const hipError_t se = le == hipSuccess ? hipStreamSynchronize(st) : le;
         (void)hipGraphExecDestroy(ex);
-        (void)hipGraphDestroy(gr);
         BQC_HIP(se);
+    } else {
+        hipEvent_t filled[2] = {make_event(false), make_event(false)};
+        hipEvent_t freed[2] = {make_event(false), make_event(false)};
+        hipEvent_t ready = make_event(false);
+        BQC_HIP(hipEventRecord(ready, st));
+        BQC_HIP(hipStreamWaitEvent(side, ready, 0));  // tables and operands are in place
+        int batch = 0;
+        for (int b0 = t_begin; b0 < t_end; b0 += plan.nb, ++batch) {
+            const int nb = std::min(plan.nb, t_end - b0);
+            const int k = batch & 1;
+            if (batch >= 2) BQC_HIP(hipStreamWaitEvent(st, freed[k], 0));
+            hipEvent_t g0 = mark(timing, st);
+            gemm_of(b0, nb, k).launch(st);
+            hipEvent_t g1 = mark(timing, st);
+            if (timing) gemm_ev.emplace_back(g0, g1);
+            BQC_HIP(hipEventRecord(filled[k], st));
+
+            BQC_HIP(hipStreamWaitEvent(side, filled[k], 0));
+            hipEvent_t p0 = mark(timing, side);
+            epi_of(b0, nb, k).launch(side);
+            hipEvent_t p1 = mark(timing, side);
+            if (timing) epi_ev.emplace_back(p0, p1);
+            reduce_triples_call(partial, nb, norbit, d_trip + b0, etrip + b0).launch(side);
+            BQC_HIP(hipEventRecord(freed[k], side));
+        }
+        hipEvent_t done_side = make_event(false);
+        BQC_HIP(hipEventRecord(done_side, side));
+        BQC_HIP(hipStreamWaitEvent(st, done_side, 0));
+        reduce_total_call(etrip + t_begin, t_end - t_begin, d_total).launch(st);
     }
     if (d_energy)
         BQC_HIP(hipMemcpyAsync(d_energy, base + L.energy, sizeof(double), hipMemcpyDeviceToDevice, st));
