@@ -142,40 +142,50 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
 
     std::vector<std::pair<hipEvent_t, hipEvent_t>> gemm_ev, epi_ev;
     if (graph) {
-        // The batch sequence as one explicitly built hipGraph: kernel nodes
-        // with the dependencies of the two-stream pipeline (no stream capture,
-        // so other threads' runtime calls cannot interfere with it):
+        // The batch sequence as explicitly built hipGraphs of at most
+        // kGraphBatches batches each, launched in order on `st`: kernel nodes
+        // with the dependencies of the two-stream pipeline and no stream
+        // capture, so other threads' runtime calls cannot interfere:
         //   gemm(b)   after gemm(b-1) and reduce(b-2)  (H buffer b mod 2 free)
         //   epi(b)    after gemm(b) and reduce(b-1)
-        //   reduce(b) after epi(b);  total after every reduce and the last gemm
-        hipGraph_t gr = nullptr;
-        BQC_HIP(hipGraphCreate(&gr, 0));
-        struct GraphGuard { hipGraph_t g; ~GraphGuard() { if (g) (void)hipGraphDestroy(g); } } gg{gr};
-        std::vector<hipGraphNode_t> red;
-        hipGraphNode_t last_gemm = nullptr;
-        int batch = 0;
-        for (int b0 = t_begin; b0 < t_end; b0 += plan.nb, ++batch) {
-            const int nb = std::min(plan.nb, t_end - b0);
-            const int k = batch & 1;
-            std::vector<hipGraphNode_t> dg;
-            if (last_gemm) dg.push_back(last_gemm);
-            if (batch >= 2) dg.push_back(red[batch - 2]);
-            last_gemm = gemm_of(b0, nb, k).add_to(gr, dg);
-            std::vector<hipGraphNode_t> de{last_gemm};
-            if (batch >= 1) de.push_back(red[batch - 1]);
-            const hipGraphNode_t ep = epi_of(b0, nb, k).add_to(gr, de);
-            red.push_back(reduce_triples_call(partial, nb, norbit, d_trip + b0, etrip + b0).add_to(gr, {ep}));
+        //   reduce(b) after epi(b)
+        // The bound keeps each graph's dependency chain short: the runtime
+        // walks a graph's dependencies depth-first when it orders the nodes,
+        // and one graph per solve (up to 3 x 11440 nodes in one chain for a
+        // 40-occupied fragment) overflowed the stack of the thread doing so.
+        constexpr int kGraphBatches = 64;
+        std::vector<hipGraphExec_t> execs;
+        struct ExecGuard {
+            std::vector<hipGraphExec_t>& e;
+            ~ExecGuard() { for (hipGraphExec_t x : e) (void)hipGraphExecDestroy(x); }
+        } eg{execs};
+        for (int c0 = t_begin; c0 < t_end; c0 += kGraphBatches * plan.nb) {
+            const int c1 = std::min(t_end, c0 + kGraphBatches * plan.nb);
+            hipGraph_t gr = nullptr;
+            BQC_HIP(hipGraphCreate(&gr, 0));
+            struct GraphGuard { hipGraph_t g; ~GraphGuard() { (void)hipGraphDestroy(g); } } gg{gr};
+            std::vector<hipGraphNode_t> red;
+            hipGraphNode_t last_gemm = nullptr;
+            int batch = 0;
+            for (int b0 = c0; b0 < c1; b0 += plan.nb, ++batch) {
+                const int nb = std::min(plan.nb, c1 - b0);
+                const int k = batch & 1;  // graphs run one after another on `st`
+                std::vector<hipGraphNode_t> dg;
+                if (last_gemm) dg.push_back(last_gemm);
+                if (batch >= 2) dg.push_back(red[batch - 2]);
+                last_gemm = gemm_of(b0, nb, k).add_to(gr, dg);
+                std::vector<hipGraphNode_t> de{last_gemm};
+                if (batch >= 1) de.push_back(red[batch - 1]);
+                const hipGraphNode_t ep = epi_of(b0, nb, k).add_to(gr, de);
+                red.push_back(reduce_triples_call(partial, nb, norbit, d_trip + b0, etrip + b0).add_to(gr, {ep}));
+            }
+            hipGraphExec_t ex = nullptr;
+            BQC_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+            execs.push_back(ex);
+            BQC_HIP(hipGraphLaunch(ex, st));
         }
-        std::vector<hipGraphNode_t> dt;
-        if (!red.empty()) dt.push_back(red.back());
-        if (last_gemm) dt.push_back(last_gemm);
-        reduce_total_call(etrip + t_begin, t_end - t_begin, d_total).add_to(gr, dt);
-        hipGraphExec_t ex = nullptr;
-        BQC_HIP(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-        const hipError_t le = hipGraphLaunch(ex, st);
-        const hipError_t se = le == hipSuccess ? hipStreamSynchronize(st) : le;
-        (void)hipGraphExecDestroy(ex);
-        BQC_HIP(se);
+        reduce_total_call(etrip + t_begin, t_end - t_begin, d_total).launch(st);
+        BQC_HIP(hipStreamSynchronize(st));
     } else {
         hipEvent_t filled[2] = {make_event(false), make_event(false)};
         hipEvent_t freed[2] = {make_event(false), make_event(false)};

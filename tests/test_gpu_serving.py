@@ -119,3 +119,23 @@ def test_graph_and_direct_launch_agree():
             ts = [srv.submit(s[0], s[1], *x.arrays()) for s, x in zip(SHAPES, xs)]
             out[graphs] = [srv.wait(t)[0] for t in ts]
     assert out[True] == out[False]
+
+
+def test_request_of_many_graphs_matches_direct_solve():
+    """A request whose triple batches span several hipGraphs (210 triples in
+    70 batches of three; a graph holds at most 64 batches) gives bitwise the
+    energy of the stream-launched single solve."""
+    import torch
+
+    import paper_2502_17963_amd as bqc
+    from synth import make_inputs_device
+    o, v, naux = 10, 304, 600
+    print(f"case many-graph request o={o} v={v}", flush=True)
+    x = make_inputs_device(o, v, naux, 77)
+    torch.cuda.synchronize()
+    e_direct = bqc.t_energy(o, v, *x, precision="bf16x3")
+    torch.cuda.synchronize()
+    with bqc.Server(precision="bf16x3", max_inflight=2, mem_budget_bytes=int(8e9)) as srv:
+        t = srv.submit(o, v, *x)
+        e_srv, st = srv.wait(t)
+    assert e_srv == e_direct
