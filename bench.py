@@ -167,7 +167,18 @@ def _serve_stream(bqc, srv, shapes, arrivals, cap_bytes, keep_idx):
     return rec, time.perf_counter() - t0, kept
 
 
+SERVING_DISABLED = (
+    "the serving benchmark is switched off: its runs with fragments generated on the GPU while the "
+    "server solves others ended in a host segmentation fault (after ~100 of 256 requests, and within "
+    "a minute for 64 requests) whose cause has not been found; the server's host logic is clean under "
+    "ThreadSanitizer and AddressSanitizer (tests/test_server_host.py) and the GPU serving tests pass")
+
+
 def run_serving(args):
+    raise SystemExit(SERVING_DISABLED)
+
+
+def _run_serving_measurement(args):
     import numpy as np
     import torch
 
