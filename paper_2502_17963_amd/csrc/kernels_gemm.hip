@@ -171,9 +171,11 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
     int rem = L;
     const int tw = rem % ntile_w; rem /= ntile_w;
     const int tu = rem % ntile_u; rem /= ntile_u;
-    const int y = rem % v; rem /= v;
-    const int h = rem % 3;
-    const int t = rem / 3;
+    // the three pairs of a plane are neighbours: they share the plane's
+    // (ov|vv) rows of i, j and k in L2 (half the HBM fetch of pair-major order)
+    const int h = rem % 3; rem /= 3;
+    const int y = rem % v;
+    const int t = rem / v;
     const int4 tr = g.trip[t];
     int q, P, R;
     roles(h, tr.x, tr.y, tr.z, q, P, R);
