@@ -56,9 +56,47 @@ def parse():
                          "with a progress line after each (0: 1, or 16 for the largest fragment)")
     ap.add_argument("--device-inputs", type=int, default=-1,
                     help="1: generate the inputs on the GPU (-1: only for the largest fragment)")
+    ap.add_argument("--df", action="store_true",
+                    help="also time the headline precision through bqc_t_energy_df, with (ia|bc) formed on "
+                         "the device from the density-fitting factors")
     ap.add_argument("--rate-frac", type=float, default=0.7,
                     help="serving open loop: arrival rate as a fraction of the closed-loop req/s (0: skip)")
     return ap.parse_args()
+
+
+def run_df(args, bqc, x, dev, prec, hr, F, naux, seed):
+    """The headline precision through bqc_t_energy_df: inputs B^Q_ia, B^Q_bc
+    (naux (o v + v^2) doubles) instead of (ia|bc) (o v^3)."""
+    import numpy as np
+    import torch
+
+    from synth import draw_factors
+    o, v = x.nocc, x.nvir
+    b = draw_factors(o, v, naux, seed)[0]
+    b_ov = torch.from_numpy(np.ascontiguousarray(b[:, :o, o:])).to("cuda:0")
+    b_vv = torch.from_numpy(np.ascontiguousarray(b[:, o:, o:])).to("cuda:0")
+    del b
+    eps_o, eps_v, t1, t2, _ovvv, ooov, ovov = dev
+    args_df = (o, v, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov)
+    for _ in range(args.warmup):
+        bqc.t_energy_df(*args_df, precision=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        e, ex = bqc.t_energy_df(*args_df, precision=prec, timing=True)
+        stats.append(ex["stats"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    rel = abs(e - hr["E_T"]) / abs(hr["E_T"])
+    rec = {"precision": prec, "E_T": e, "s": round(dt, 4), "tflops": round(F / dt / 1e12, 3),
+           "prepare_s": round(sum(s["prepare_s"] for s in stats) / len(stats), 4),
+           "prepare_s_with_ovvv_input": round(hr.get("prepare_s", 0.0), 4),
+           "rel_vs_ovvv_input": rel,
+           "input_bytes_ovvv": 8 * o * v ** 3, "input_bytes_factors": 8 * naux * (o * v + v * v)}
+    print(f"[bench] density fitting {prec}: E_T={e:.12e} rel vs (ia|bc) input {rel:.2e} {dt:.2f} s/step "
+          f"{F / dt / 1e12:.2f} TFLOP/s, prepare {rec['prepare_s']:.3f} s", file=sys.stderr, flush=True)
+    return rec
 
 
 def kernel_source_hash() -> str:
@@ -399,6 +437,8 @@ def main():
                      "mfma_products_per_flop": MFMA_PER_FLOP[head],
                      "mfma_pipe_frac": round(achieved * MFMA_PER_FLOP[head] / peak, 4)},
     }
+    if args.df and x is not None:
+        out["density_fitting"] = run_df(args, bqc, x, dev, head, hr, F, naux, seed)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
     line = json.dumps(out)

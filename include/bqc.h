@@ -118,6 +118,28 @@ int bqc_t_energy_ex(int32_t nocc, int32_t nvir,
                     const double* ovvv, const double* ooov, const double* ovov,
                     const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats);
 
+/*
+ * Single solve with (ia|bc) formed on the device from density-fitting
+ * factors (paper section 2.2: (pq|rs) = sum_Q B^Q_pq B^Q_rs) instead of being
+ * passed as the o*v^3 array:
+ *   b_ov  [naux][nocc][nvir]  = B^Q_ia        (row-major, FP64)
+ *   b_vv  [naux][nvir][nvir]  = B^Q_bc        (symmetric in b, c)
+ * The other inputs, the options (inputs_on_device applies to b_ov and b_vv
+ * too), the outputs and the error codes are those of bqc_t_energy_ex; naux
+ * must be >= 1 and b_ov, b_vv non-NULL (else BQC_EINVAL).  The product over Q
+ * runs in FP64 on the device for a few occupied indices at a time and goes
+ * straight into the contraction operand of the chosen precision, so no
+ * o*v^3 FP64 array is held (device memory for it: a bounded scratch of at
+ * most max(v^3, 2^26) doubles).  E_T equals bqc_t_energy_ex's with
+ * ovvv = sum_Q b_ov b_vv up to the rounding of that product.
+ */
+int bqc_t_energy_df(int32_t nocc, int32_t nvir, int32_t naux,
+                    const double* eps_o, const double* eps_v,
+                    const double* t1, const double* t2,
+                    const double* b_ov, const double* b_vv,
+                    const double* ooov, const double* ovov,
+                    const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats);
+
 /* Number of unique occupied triples for nocc (0 for nocc < 1). */
 int64_t bqc_t_num_triples(int32_t nocc);
 

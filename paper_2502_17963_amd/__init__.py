@@ -13,8 +13,9 @@ from .binding import (  # noqa: F401
     lib,
     num_triples,
     t_energy,
+    t_energy_df,
     t_energy_plain,
 )
 
 __all__ = ["BqcError", "Server", "PRECISIONS", "footprint", "header_functions", "last_error", "lib",
-           "num_triples", "t_energy", "t_energy_plain"]
+           "num_triples", "t_energy", "t_energy_df", "t_energy_plain"]

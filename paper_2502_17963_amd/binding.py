@@ -84,6 +84,9 @@ def lib():
             L.bqc_t_energy_ex.argtypes = [ctypes.c_int32, ctypes.c_int32, *seven,
                                           ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
             L.bqc_t_energy_ex.restype = ctypes.c_int
+            L.bqc_t_energy_df.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, *([_dp] * 8),
+                                          ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
+            L.bqc_t_energy_df.restype = ctypes.c_int
             L.bqc_t_num_triples.argtypes = [ctypes.c_int32]
             L.bqc_t_num_triples.restype = ctypes.c_int64
             L.bqc_t_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -182,6 +185,43 @@ def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64
     e = ctypes.c_double(0.0)
     st = TStats()
     rc = lib().bqc_t_energy_ex(nocc, nvir, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
+    del keep
+    _check(rc)
+    if not (triple_energies or stats or timing):
+        return e.value
+    extras = {}
+    if triple_energies:
+        extras["triples"] = etrip[:num_triples(nocc)]
+    extras["stats"] = st.as_dict()
+    return e.value, extras
+
+
+def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, precision="fp64",
+                device=0, triple_energies=False, timing=False, stream=None, stats=False, triple_range=None):
+    """E_T through bqc_t_energy_df: (ia|bc) formed on the device from the
+    density-fitting factors b_ov[naux][nocc][nvir] and b_vv[naux][nvir][nvir].
+    Arguments and results as t_energy."""
+    arrays = (eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov)
+    ptrs, on_dev, keep = _ptrs(arrays)
+    opts = TOpts()
+    opts.precision = _prec(precision)
+    opts.device = device
+    opts.inputs_on_device = 1 if on_dev else 0
+    opts.timing = 1 if timing else 0
+    if triple_range is not None:
+        opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
+    if stream is not None:
+        opts.stream = ctypes.c_void_p(stream)
+    elif on_dev:
+        import torch
+        opts.stream = ctypes.c_void_p(torch.cuda.current_stream(arrays[0].device).cuda_stream)
+    etrip = None
+    if triple_energies:
+        etrip = np.zeros(max(num_triples(nocc), 1))
+        opts.triple_energies = etrip.ctypes.data_as(_dp)
+    e = ctypes.c_double(0.0)
+    st = TStats()
+    rc = lib().bqc_t_energy_df(nocc, nvir, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
     del keep
     _check(rc)
     if not (triple_energies or stats or timing):

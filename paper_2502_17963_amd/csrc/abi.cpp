@@ -55,6 +55,8 @@ struct Ctx {
     void* in = nullptr;
     size_t in_size = 0;
     double* host_energy = nullptr;  // pinned 8 bytes
+    void* df_tmp = nullptr;         // FP64 scratch of the density-fitting product
+    size_t df_tmp_size = 0;
     bool busy = false;
 };
 
@@ -96,16 +98,21 @@ struct DeviceGuard {
 
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// One solve.  df = false: (ia|bc) is the input ovvv; df = true: it is formed
+// on the device from the density-fitting factors b_ov, b_vv (naux of them).
 int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, const double* t1,
                const double* t2, const double* ovvv, const double* ooov, const double* ovov,
-               const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats) {
+               const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats, bool df = false,
+               int32_t naux = 0, const double* b_ov = nullptr, const double* b_vv = nullptr) {
     bqc_t_opts op;
     std::memset(&op, 0, sizeof(op));
     if (opts) op = *opts;
     if (!E_T) return fail(BQC_EINVAL, "E_T is null");
     if (op.precision < 0 || op.precision > 3) return fail(BQC_EINVAL, "unknown precision");
     const bool dev_in = op.inputs_on_device != 0;
-    int rc = validate(o, v, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, !dev_in);
+    if (df && (naux < 1 || !b_ov || !b_vv))
+        return fail(BQC_EINVAL, "density fitting needs naux >= 1 and non-null b_ov, b_vv");
+    int rc = validate(o, v, eps_o, eps_v, t1, t2, df ? b_ov : ovvv, ooov, ovov, !dev_in);
     if (rc != BQC_OK) return rc;
     const int64_t ntrip_all = num_triples(o);
     if (op.triple_end == 0 ? op.triple_begin != 0
@@ -129,36 +136,51 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         BQC_HIP(hipMemcpyAsync(eo.data(), eps_o, o * sizeof(double), hipMemcpyDeviceToHost, st));
         BQC_HIP(hipMemcpyAsync(evv.data(), eps_v, v * sizeof(double), hipMemcpyDeviceToHost, st));
         BQC_HIP(hipStreamSynchronize(st));
-        rc = validate(o, v, eo.data(), evv.data(), t1, t2, ovvv, ooov, ovov, true);
+        rc = validate(o, v, eo.data(), evv.data(), t1, t2, df ? b_ov : ovvv, ooov, ovov, true);
         if (rc != BQC_OK) return rc;
     }
 
     const int64_t ntrip = num_triples(o);
-    const size_t sizes[7] = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v,
-                             (size_t)o * v * v * v, (size_t)o * o * o * v, (size_t)o * v * o * v};
-    DevInputs in;
-    in.o = o;
-    in.v = v;
-    double upload_s = 0.0;
-    if (dev_in) {
-        in.eps_o = eps_o; in.eps_v = eps_v; in.t1 = t1; in.t2 = t2;
-        in.ovvv = ovvv; in.ooov = ooov; in.ovov = ovov;
+    // inputs: eps_o, eps_v, t1, t2, [ovvv | b_ov, b_vv], ooov, ovov
+    std::vector<const double*> src = {eps_o, eps_v, t1, t2};
+    std::vector<size_t> sizes = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v};
+    if (df) {
+        src.push_back(b_ov); sizes.push_back((size_t)naux * o * v);
+        src.push_back(b_vv); sizes.push_back((size_t)naux * v * v);
     } else {
-        size_t need = 0;
-        for (size_t s : sizes) need += a256(s * sizeof(double));
-        ensure(ctx->in, ctx->in_size, need);
-        const double* src[7] = {eps_o, eps_v, t1, t2, ovvv, ooov, ovov};
-        const double* dst[7];
+        src.push_back(ovvv); sizes.push_back((size_t)o * v * v * v);
+    }
+    src.push_back(ooov); sizes.push_back((size_t)o * o * o * v);
+    src.push_back(ovov); sizes.push_back((size_t)o * v * o * v);
+    std::vector<const double*> dst(src.size());
+    double upload_s = 0.0;
+    size_t in_bytes = 0;
+    if (dev_in) {
+        dst = src;
+    } else {
+        for (size_t s : sizes) in_bytes += a256(s * sizeof(double));
+        ensure(ctx->in, ctx->in_size, in_bytes);
         char* p = (char*)ctx->in;
         auto u0 = std::chrono::steady_clock::now();
-        for (int a = 0; a < 7; ++a) {
+        for (size_t a = 0; a < src.size(); ++a) {
             BQC_HIP(hipMemcpyAsync(p, src[a], sizes[a] * sizeof(double), hipMemcpyHostToDevice, st));
             dst[a] = (const double*)p;
             p += a256(sizes[a] * sizeof(double));
         }
         BQC_HIP(hipStreamSynchronize(st));
         upload_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - u0).count();
-        in.eps_o = dst[0]; in.eps_v = dst[1]; in.t1 = dst[2]; in.t2 = dst[3];
+    }
+    DevInputs in;
+    in.o = o;
+    in.v = v;
+    in.eps_o = dst[0]; in.eps_v = dst[1]; in.t1 = dst[2]; in.t2 = dst[3];
+    if (df) {
+        in.b_ov = dst[4]; in.b_vv = dst[5]; in.naux = naux;
+        in.ooov = dst[6]; in.ovov = dst[7];
+        ensure(ctx->df_tmp, ctx->df_tmp_size, (size_t)df_scratch_elems(o, v) * sizeof(double));
+        in.df_tmp = (double*)ctx->df_tmp;
+        in.df_block = df_block_planes(o, v);
+    } else {
         in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
     }
 
@@ -190,7 +212,8 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         stats->epilogue_s = ss.epi_s;
         stats->gemm_launches = ss.gemm_launches;
         stats->epilogue_launches = ss.epi_launches;
-        stats->footprint_bytes = ss.footprint + (dev_in ? 0 : (uint64_t)input_bytes(o, v));
+        stats->footprint_bytes = ss.footprint + in_bytes +
+                                 (df ? (uint64_t)df_scratch_elems(o, v) * sizeof(double) : 0);
         stats->flops = 12.0 * (double)nshare * (double)v * v * v * (double)(v + o);
         stats->precision = op.precision;
         stats->n_triples = (int32_t)nshare;
@@ -233,6 +256,18 @@ int bqc_t_energy_ex(int32_t nocc, int32_t nvir, const double* eps_o, const doubl
                     const double* ovov, const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats) {
     return guarded([&] {
         return solve_impl(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, opts, E_T, stats);
+    });
+}
+
+int bqc_t_energy_df(int32_t nocc, int32_t nvir, int32_t naux, const double* eps_o, const double* eps_v,
+                    const double* t1, const double* t2, const double* b_ov, const double* b_vv,
+                    const double* ooov, const double* ovov, const bqc_t_opts* opts, double* E_T,
+                    bqc_t_stats* stats) {
+    return guarded([&] {
+        if (!b_ov || !b_vv || naux < 1)
+            return fail(BQC_EINVAL, "density fitting needs naux >= 1 and non-null b_ov, b_vv");
+        return solve_impl(nocc, nvir, eps_o, eps_v, t1, t2, nullptr, ooov, ovov, opts, E_T, stats, true, naux,
+                          b_ov, b_vv);
     });
 }
 

@@ -60,9 +60,16 @@ struct DevInputs {
     const double* eps_v = nullptr;
     const double* t1 = nullptr;
     const double* t2 = nullptr;
-    const double* ovvv = nullptr;
+    const double* ovvv = nullptr;  // nullptr: formed from b_ov, b_vv (density fitting)
     const double* ooov = nullptr;
     const double* ovov = nullptr;
+    // density-fitting factors b_ov[naux][o][v], b_vv[naux][v][v] and the FP64
+    // scratch for df_block occupied planes (o-slices of (ov|vv)) at a time
+    const double* b_ov = nullptr;
+    const double* b_vv = nullptr;
+    int naux = 0;
+    double* df_tmp = nullptr;
+    int df_block = 0;
 };
 
 // Contraction operands in the contraction precision (a1), chunk-major: a
@@ -172,6 +179,10 @@ struct KernelCall {
 void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* ops,
                     hipStream_t st);
 int64_t prepare_bytes(int precision, int o, int v);
+// Occupied planes of (ov|vv) formed per pass of the density-fitting product,
+// and the scratch (doubles) they need.
+int df_block_planes(int o, int v);
+int64_t df_scratch_elems(int o, int v);
 
 KernelCall gemm_call(int precision, const GemmLaunch& g);
 int wave_blocks(int v);  // contraction wave tile (16-blocks per side) used for this v

@@ -17,6 +17,8 @@
 // split-BF16x3 mode a chunk holds 32 bf16 hi parts followed by their 32 lo
 // parts (x_hi = bf16(x), x_lo = bf16(x - x_hi)).  The FP8 mode pads to 128
 // and stores 128 e4m3 bytes per chunk row plus one E8M0 exponent per 32.
+#include <algorithm>
+
 #include "bqc_internal.h"
 
 namespace bqc {
@@ -168,7 +170,94 @@ void launch_factor_fp8(const double* src, void* dst, void* scl, int64_t nmat, in
 
 void prepare_fp8(const DevInputs& in, void* ws, Operands* ops, hipStream_t st);
 
+// Density fitting of (ov|vv) (paper section 2.2) for the occupied indices
+// P0 <= P < P0 + np:  out[P - P0][u][n] = sum_Q b_ov[Q][P][u] b_vv[Q][n],
+// n = y v + d, i.e. out holds ovvv[P][u][y][d] for the block.  FP64 MFMA
+// 16x16x4 on 64 x 64 (u, n) tiles, 16 values of Q staged through LDS per step.
+constexpr int DF_T = 64, DF_K = 16;
+
+__global__ __launch_bounds__(256) void df_ovvv_kernel(const double* __restrict__ b_ov,
+                                                      const double* __restrict__ b_vv, double* __restrict__ out,
+                                                      int o, int v, int naux, int P0) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    const int64_t v2 = (int64_t)v * v;
+    const int64_t n0 = (int64_t)blockIdx.x * DF_T;
+    const int u0 = blockIdx.y * DF_T, P = P0 + (int)blockIdx.z;
+    __shared__ double As[DF_K][DF_T];  // As[k][u] = b_ov[Q0 + k][P][u0 + u]
+    __shared__ double Bs[DF_K][DF_T];  // Bs[k][n] = b_vv[Q0 + k][n0 + n]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;  // this wave's 32 x 32 block
+    const int fr = lane & 15, fg = lane >> 4;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+    for (int Q0 = 0; Q0 < naux; Q0 += DF_K) {
+        double ra[4], rb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + 256 * i, k = idx / DF_T, m = idx % DF_T;
+            const int Q = Q0 + k;
+            ra[i] = (Q < naux && u0 + m < v) ? b_ov[((int64_t)Q * o + P) * v + u0 + m] : 0.0;
+            rb[i] = (Q < naux && n0 + m < v2) ? b_vv[(int64_t)Q * v2 + n0 + m] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int idx = tid + 256 * i;
+            As[idx / DF_T][idx % DF_T] = ra[i];
+            Bs[idx / DF_T][idx % DF_T] = rb[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < DF_K / 4; ++s) {
+            // operand of lane (fr, fg): row fr of the 16-block, contraction index 4 s + fg
+            double a[2], b[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                a[x] = As[4 * s + fg][wm + 16 * x + fr];
+                b[x] = Bs[4 * s + fg][wn + 16 * x + fr];
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+    }
+    // FP64 accumulator layout: register r of lane l holds row (l / 16) + 4 r, column l % 16
+    double* o_p = out + (int64_t)blockIdx.z * v * v2;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int u = u0 + wm + 16 * x + fg + 4 * r;
+                const int64_t n = n0 + wn + 16 * y + fr;
+                if (u < v && n < v2) o_p[(int64_t)u * v2 + n] = acc[x][y][r];
+            }
+}
+
+void launch_df_ovvv(const DevInputs& in, int P0, int np, hipStream_t st) {
+    const int64_t v2 = (int64_t)in.v * in.v;
+    const dim3 grid((unsigned)((v2 + DF_T - 1) / DF_T), (unsigned)ceil_div(in.v, DF_T), (unsigned)np);
+    hipLaunchKernelGGL(df_ovvv_kernel, grid, dim3(256), 0, st, in.b_ov, in.b_vv, in.df_tmp, in.o, in.v, in.naux,
+                       P0);
+    BQC_HIP(hipGetLastError());
+}
+
 }  // namespace
+
+int df_block_planes(int o, int v) {
+    const int64_t v3 = (int64_t)v * v * v;
+    const int64_t cap = (int64_t)1 << 26;  // 512 MB of FP64 scratch
+    int64_t b = cap / std::max<int64_t>(v3, 1);
+    b = std::max<int64_t>(1, std::min<int64_t>(b, o));
+    return (int)b;
+}
+int64_t df_scratch_elems(int o, int v) { return (int64_t)df_block_planes(o, v) * v * v * v; }
+
 
 Sizes factor_sizes(int o, int v, int precision) {
     const int kp = kpad_of(precision);
@@ -202,7 +291,16 @@ void prepare_t(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
     void* d_t2 = p;   p += align256((size_t)z.m_t2 * v * z.Kv * eb);
     void* d_t2l = p;  p += align256((size_t)z.m_t2l * v * z.Ko * eb);
     void* d_hoo = p;
-    launch_factor<PREC, F_OVVV>(in.ovvv, d_ovvv, z.m_ovvv, v, z.Kv, o, v, st);
+    if (in.ovvv) {
+        launch_factor<PREC, F_OVVV>(in.ovvv, d_ovvv, z.m_ovvv, v, z.Kv, o, v, st);
+    } else {  // density fitting, df_block occupied planes at a time through the scratch
+        for (int P0 = 0; P0 < o; P0 += in.df_block) {
+            const int np = std::min(in.df_block, o - P0);
+            launch_df_ovvv(in, P0, np, st);
+            launch_factor<PREC, F_OVVV>(in.df_tmp, (char*)d_ovvv + (size_t)P0 * v * v * z.Kv * eb,
+                                        (int64_t)np * v, v, z.Kv, o, v, st);
+        }
+    }
     launch_factor<PREC, F_T2>(in.t2, d_t2, z.m_t2, v, z.Kv, o, v, st);
     launch_factor<PREC, F_T2L>(in.t2, d_t2l, z.m_t2l, o, z.Ko, o, v, st);
     launch_factor<PREC, F_HOO>(in.ooov, d_hoo, z.m_hoo, o, z.Ko, o, v, st);
@@ -227,7 +325,17 @@ void prepare_fp8(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
     void* s_t2 = p;   p += align256((size_t)z.m_t2 * v * z.Kv / 32);
     void* s_t2l = p;  p += align256((size_t)z.m_t2l * v * z.Ko / 32);
     void* s_hoo = p;
-    launch_factor_fp8<F_OVVV>(in.ovvv, d_ovvv, s_ovvv, z.m_ovvv, v, z.Kv, o, v, st);
+    if (in.ovvv) {
+        launch_factor_fp8<F_OVVV>(in.ovvv, d_ovvv, s_ovvv, z.m_ovvv, v, z.Kv, o, v, st);
+    } else {
+        for (int P0 = 0; P0 < o; P0 += in.df_block) {
+            const int np = std::min(in.df_block, o - P0);
+            launch_df_ovvv(in, P0, np, st);
+            launch_factor_fp8<F_OVVV>(in.df_tmp, (char*)d_ovvv + (size_t)P0 * v * v * z.Kv,
+                                      (char*)s_ovvv + (size_t)P0 * v * v * z.Kv / 32, (int64_t)np * v, v, z.Kv,
+                                      o, v, st);
+        }
+    }
     launch_factor_fp8<F_T2>(in.t2, d_t2, s_t2, z.m_t2, v, z.Kv, o, v, st);
     launch_factor_fp8<F_T2L>(in.t2, d_t2l, s_t2l, z.m_t2l, o, z.Ko, o, v, st);
     launch_factor_fp8<F_HOO>(in.ooov, d_hoo, s_hoo, z.m_hoo, o, z.Ko, o, v, st);

@@ -111,6 +111,19 @@ def make_inputs(nocc: int, nvir: int, naux: int, seed: int) -> TInputs:
                    np.ascontiguousarray(ovov))
 
 
+def make_df_inputs(nocc: int, nvir: int, naux: int, seed: int):
+    """The inputs of make_inputs(nocc, nvir, naux, seed) with (ia|bc) replaced
+    by its density-fitting factors: returns (eps_o, eps_v, t1, t2, b_ov, b_vv,
+    ooov, ovov), b_ov[Q][i][a] = B[Q, i, nocc + a], b_vv[Q][b][c] = B[Q,
+    nocc + b, nocc + c] of the same draw (so sum_Q b_ov b_vv is the ovvv of
+    make_inputs up to the rounding of the product)."""
+    b, eps_o, eps_v, t1 = draw_factors(nocc, nvir, naux, seed)
+    x = make_inputs(nocc, nvir, naux, seed)
+    b_ov = np.ascontiguousarray(b[:, :nocc, nocc:])
+    b_vv = np.ascontiguousarray(b[:, nocc:, nocc:])
+    return (x.eps_o, x.eps_v, x.t1, x.t2, b_ov, b_vv, x.ooov, x.ovov)
+
+
 def serving_stream(n_requests: int = 256, seed: int = 4, rate: float | None = None):
     """Fragment shapes for the serving workload.
 
@@ -158,14 +171,17 @@ def _check() -> None:  # pragma: no cover - tiny self check
     assert math.isfinite(float(x.t2.sum()))
 
 
-def make_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:0"):
+def make_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:0", factors=False):
     """Same recipe as make_inputs, generated on a HIP device with torch.
 
     For the serving workload, whose 256 fragments hold ~1 TB of FP64 inputs in
     total: each fragment is generated on the GPU when it arrives.  The draws
     come from torch's device generator seeded with `seed`, so the values
     differ from make_inputs(…, seed) (a different random stream with the same
-    distributions).  Returns the seven ABI arrays as contiguous FP64 tensors.
+    distributions).  Returns the seven ABI arrays as contiguous FP64 tensors;
+    with factors=True, (ia|bc) is not formed and the eight arrays of the
+    density-fitting entry are returned instead: (eps_o, eps_v, t1, t2, b_ov,
+    b_vv, ooov, ovov) with b_ov[Q][i][a], b_vv[Q][b][c].
     """
     import torch
     g = torch.Generator(device=device)
@@ -182,11 +198,15 @@ def make_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:
     b_ov = b[:, :nocc, nocc:].reshape(naux, nocc * nvir)
     b_vv = b[:, nocc:, nocc:].reshape(naux, nvir * nvir).contiguous()
     b_ovt = b_ov.t().contiguous()
-    ovvv = (b_ovt @ b_vv).reshape(nocc, nvir, nvir, nvir)
+    ovvv = None if factors else (b_ovt @ b_vv).reshape(nocc, nvir, nvir, nvir)
     ooov = (b_oo @ b_ov.contiguous()).reshape(nocc, nocc, nocc, nvir)
     ovov = (b_ovt @ b_ov.contiguous()).reshape(nocc, nvir, nocc, nvir)
+    f_ov = b_ov.reshape(naux, nocc, nvir).contiguous() if factors else None
+    f_vv = b_vv.reshape(naux, nvir, nvir) if factors else None
     del b, b_oo, b_ov, b_vv, b_ovt
     denom = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
              - eps_v[None, None, :, None] - eps_v[None, None, None, :])
     t2 = (ovov.permute(0, 2, 1, 3) / denom).contiguous()
+    if factors:
+        return tuple(a.contiguous() for a in (eps_o, eps_v, t1, t2, f_ov, f_vv, ooov, ovov))
     return tuple(a.contiguous() for a in (eps_o, eps_v, t1, t2, ovvv, ooov, ovov))

@@ -75,6 +75,26 @@ def test_triple_range_checks():
         assert "triple range" in bqc.last_error()
 
 
+def test_density_fitting_argument_checks():
+    from synth import make_df_inputs
+    a = [np.ascontiguousarray(x) for x in make_df_inputs(3, 5, 10, 0)]
+    L = bqc.lib()
+
+    def call(naux, arrays):
+        ptrs = [None if x is None else x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for x in arrays]
+        e = ctypes.c_double(123.0)
+        opts = binding.TOpts()
+        rc = L.bqc_t_energy_df(3, 5, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), None)
+        return rc, e.value
+
+    assert call(0, a) == (binding.EINVAL, 123.0)
+    assert "naux" in bqc.last_error()
+    for k in range(8):
+        bad = list(a)
+        bad[k] = None
+        assert call(10, bad) == (binding.EINVAL, 123.0), k
+
+
 def test_gap_and_finiteness_checks():
     x = make_inputs(3, 5, 10, 0)
     eo = x.eps_o.copy()

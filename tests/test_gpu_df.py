@@ -1,0 +1,80 @@
+"""(ia|bc) formed on the device from density-fitting factors
+(bqc_t_energy_df, paper section 2.2) against the oracle's stored energies and
+against the solve that takes (ia|bc) as an input."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth import make_df_inputs, make_inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_values.json")))
+
+
+def _bqc():
+    import paper_2502_17963_amd as bqc
+    bqc.lib()
+    return bqc
+
+
+def _golden(o, v, naux, seed):
+    for c in GOLDEN["cases"]:
+        if (c["nocc"], c["nvir"], c["naux"], c["seed"]) == (o, v, naux, seed):
+            return c
+    raise KeyError((o, v, naux, seed))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_df_fp64_matches_oracle(seed):
+    bqc = _bqc()
+    print(f"case df small seed={seed}", flush=True)
+    a = make_df_inputs(6, 30, 120, seed)
+    ref = _golden(6, 30, 120, seed)
+    e, ex = bqc.t_energy_df(6, 30, 120, *a, precision="fp64", triple_energies=True)
+    assert abs(e - ref["E_T"]) <= 1e-10 * abs(ref["E_T"])
+    trip = np.array(ref["triples"])
+    assert np.max(np.abs(ex["triples"] - trip)) <= 1e-10 * np.max(np.abs(trip))
+
+
+# (nocc, nvir, naux, seed): ragged tiles, one occupied orbital, several DF passes
+SHAPES = [(2, 17, 40, 5), (5, 37, 100, 3), (7, 45, 150, 2), (1, 9, 20, 6), (4, 64, 160, 1)]
+REL = {"fp64": 1e-12, "fp32": 1e-7, "bf16x3": 1e-7, "fp8": 1e-2}
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp8"])
+def test_df_matches_ovvv_input(shape, prec):
+    """Same precision, (ia|bc) from the factors vs passed in: the operands
+    differ only by the rounding of the FP64 product over Q."""
+    bqc = _bqc()
+    o, v, naux, seed = shape
+    print(f"case df {prec} o={o} v={v} naux={naux}", flush=True)
+    a = make_df_inputs(o, v, naux, seed)
+    x = make_inputs(o, v, naux, seed)
+    e_df = bqc.t_energy_df(o, v, naux, *a, precision=prec)
+    e_in = bqc.t_energy(o, v, *x.arrays(), precision=prec)
+    scale = max(abs(e_in), 1e-300)
+    assert abs(e_df - e_in) <= REL[prec] * scale, (e_df, e_in)
+
+
+def test_df_device_factors():
+    """Device-resident factors on the caller's stream, several planes per pass
+    (nvir = 100: the scratch holds 67 planes, so o = 8 is one pass) and the
+    multi-pass case (nvir = 420: one plane per pass)."""
+    import torch
+
+    from synth import make_inputs_device
+    bqc = _bqc()
+    for (o, v, naux) in [(8, 100, 300), (3, 420, 500)]:
+        print(f"case df device o={o} v={v} naux={naux}", flush=True)
+        f = make_inputs_device(o, v, naux, 11, factors=True)
+        x = make_inputs_device(o, v, naux, 11)
+        torch.cuda.synchronize()
+        e_df = bqc.t_energy_df(o, v, naux, *f, precision="fp64")
+        e_in = bqc.t_energy(o, v, *x, precision="fp64")
+        torch.cuda.synchronize()
+        assert abs(e_df - e_in) <= 1e-12 * abs(e_in), (o, v, e_df, e_in)
+        del f, x

@@ -54,3 +54,25 @@ def test_mixed_totals_against_fp64(large, prec):
     rel = abs(e - e64) / abs(e64)
     print(f"{prec}: E={e:.12e} fp64={e64:.12e} rel={rel:.3e} dE={abs(e - e64) * 1e6:.3e} uEh", flush=True)
     assert rel <= 1e-6
+
+
+def test_df_bf16x3_matches_ovvv_input(large):
+    """Density-fitting entry at the benchmarked size: (ia|bc) formed on the
+    device from B (draw of the same seed) gives the energy of the solve that
+    takes (ia|bc) as an input, to the mixed-precision gate."""
+    import torch
+
+    from synth import draw_factors
+    bqc, x, dev, e64, _ = large
+    o, v = x.nocc, x.nvir
+    b = draw_factors(o, v, 1000, 0)[0]
+    b_ov = torch.from_numpy(np.ascontiguousarray(b[:, :o, o:])).to("cuda:0")
+    b_vv = torch.from_numpy(np.ascontiguousarray(b[:, o:, o:])).to("cuda:0")
+    del b
+    eps_o, eps_v, t1, t2, _ovvv, ooov, ovov = dev
+    e_df = bqc.t_energy_df(o, v, 1000, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, precision="bf16x3")
+    e_in = bqc.t_energy(o, v, *dev, precision="bf16x3")
+    torch.cuda.synchronize()
+    print(f"df bf16x3 E={e_df:.12e} ovvv-input E={e_in:.12e} fp64 {e64:.12e}", flush=True)
+    assert abs(e_df - e_in) <= 1e-7 * abs(e_in)
+    assert abs(e_df - e64) <= 1e-6 * abs(e64)
