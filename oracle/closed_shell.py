@@ -44,7 +44,11 @@ Readings of the paper's equations (they are garbled in the text):
  4. "P = sum over all permutations of abc" is the sum over the six
     simultaneous permutations of the index pairs.
  5. The Fock term x_k F_ck of Eqs. 5 and 7 vanishes for a canonical HF
-    reference (f_ov = 0) and is not computed.
+    reference (f_ov = 0).  For a reference with diagonal occupied and
+    virtual Fock blocks (orbital energies e) but f_ov != 0 it enters, like
+    the singles term, through V:
+        V_abc += f_ia t_jk^bc + f_jb t_ik^ac + f_kc t_ij^ab
+    (fock_ov[i][a] = f_ia; optional argument, None = canonical).
  6. The singles term y_k t_k^c of Eqs. 6-7 is folded into V above: because
     the operator in Z is symmetric under the sum over abc, the two routes
     give the same energy.
@@ -101,12 +105,17 @@ def w_tensor(i, j, k, t2, ovvv, ooov):
     return w
 
 
-def v_tensor(i, j, k, w, t1, ovov):
-    """V_abc = W_abc + t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)."""
+def v_tensor(i, j, k, w, t1, ovov, t2=None, fock_ov=None):
+    """V_abc = W_abc + t_i^a (jb|kc) + t_j^b (ia|kc) + t_k^c (ia|jb)
+             [+ f_ia t_jk^bc + f_jb t_ik^ac + f_kc t_ij^ab  if fock_ov is given]."""
     v = w.copy()
     v += t1[i][:, None, None] * ovov[j, :, k, :][None, :, :]
     v += t1[j][None, :, None] * ovov[i, :, k, :][:, None, :]
     v += t1[k][None, None, :] * ovov[i, :, j, :][:, :, None]
+    if fock_ov is not None:
+        v += fock_ov[i][:, None, None] * t2[j, k][None, :, :]
+        v += fock_ov[j][None, :, None] * t2[i, k][:, None, :]
+        v += fock_ov[k][None, None, :] * t2[i, j][:, :, None]
     return v
 
 
@@ -123,20 +132,20 @@ def z_tensor(i, j, k, v, eps_o, eps_v):
     return num / d
 
 
-def triple_energy(i, j, k, m, eps_o, eps_v, t1, t2, ovvv, ooov, ovov):
+def triple_energy(i, j, k, m, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, fock_ov=None):
     """e_ijk = (m/3) sum_abc W_abc Z_abc for one unique triple."""
     w = w_tensor(i, j, k, t2, ovvv, ooov)
-    v = v_tensor(i, j, k, w, t1, ovov)
+    v = v_tensor(i, j, k, w, t1, ovov, t2, fock_ov)
     z = z_tensor(i, j, k, v, eps_o, eps_v)
     return (m / 3.0) * float(np.sum(w * z))
 
 
-def t_energy(eps_o, eps_v, t1, t2, ovvv, ooov, ovov, return_triples=False):
+def t_energy(eps_o, eps_v, t1, t2, ovvv, ooov, ovov, return_triples=False, fock_ov=None):
     """E_T, summed over unique triples with math.fsum (exactly rounded)."""
     nocc = t1.shape[0]
     terms = []
     for (i, j, k, m) in triple_table(nocc):
-        terms.append(triple_energy(i, j, k, m, eps_o, eps_v, t1, t2, ovvv, ooov, ovov))
+        terms.append(triple_energy(i, j, k, m, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, fock_ov))
     e = math.fsum(terms)
     if return_triples:
         return e, terms

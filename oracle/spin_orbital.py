@@ -15,7 +15,10 @@ Spin orbitals P = (p, s), s in {alpha, beta}; index 2p + s.
   t_IJ^AB   = t_ij^ab d(s_I,s_A) d(s_J,s_B) - t_ij^ba d(s_I,s_B) d(s_J,s_A)
   D_IJK^ABC = f_I + f_J + f_K - f_A - f_B - f_C
   D t(c)    = P(I/JK) P(A/BC) [ sum_E t_JK^AE <EI||BC> - sum_M t_IM^BC <MA||JK> ]
-  D t(d)    = P(I/JK) P(A/BC) t_I^A <JK||BC>
+  D t(d)    = P(I/JK) P(A/BC) [ t_I^A <JK||BC> + f_IA t_JK^BC ]
+              (f_IA = f_ia d(s_I,s_A): the occupied-virtual Fock block of a
+              non-canonical reference with diagonal oo and vv blocks; zero,
+              and the term absent, for canonical HF)
   P(I/JK) f(IJK) = f(IJK) - f(JIK) - f(KJI)
   E_T       = (1/36) sum t(c) D (t(c) + t(d))
 
@@ -50,8 +53,9 @@ def _p_vir(t):
     return (t - np.einsum("ijkBAC->ijkABC", t) - np.einsum("ijkCBA->ijkABC", t))
 
 
-def spinorb_t_energy(eps_o, eps_v, t1, t2, ovvv, ooov, ovov):
-    """E_T from the spin-orbital definition (tiny systems only)."""
+def spinorb_t_energy(eps_o, eps_v, t1, t2, ovvv, ooov, ovov, fock_ov=None):
+    """E_T from the spin-orbital definition (tiny systems only); fock_ov[i][a]
+    = f_ia adds the f_ov t2 part of the disconnected triples."""
     nocc, nvir = t1.shape
     so, sv = 2 * nocc, 2 * nvir
     if so * sv > 8 * 12 + 1e-9 and (so ** 3) * (sv ** 3) > 3.0e6:
@@ -99,5 +103,8 @@ def spinorb_t_energy(eps_o, eps_v, t1, t2, ovvv, ooov, ovov):
             - np.einsum("IMBC,MAJK->IJKABC", t2s, g_ovoo))
     tc = _p_vir(_p_occ(conn)) / dnm
     disc = np.einsum("IA,JKBC->IJKABC", t1s, g_oovv)
+    if fock_ov is not None:
+        fs = fock_ov[o_sp][:, v_sp] * d(o_s, v_s)
+        disc = disc + np.einsum("IA,JKBC->IJKABC", fs, t2s)
     td = _p_vir(_p_occ(disc)) / dnm
     return float(np.sum(tc * dnm * (tc + td)) / 36.0)

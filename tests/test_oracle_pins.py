@@ -157,6 +157,53 @@ def test_size_extensivity_two_fragments():
     assert _rel(eab, ea + eb) < 1e-12
 
 
+# ------------------------------------------------- non-canonical Fock term (f_ov)
+
+FOCK = [(2, 3, 8, 7), (3, 5, 12, 0), (2, 6, 14, 1), (4, 4, 10, 2), (3, 6, 16, 3)]
+
+
+def _fock(o, v, seed):
+    return np.random.default_rng(1000 + seed).normal(0.0, 0.02, (o, v))
+
+
+@pytest.mark.parametrize("o,v,naux,seed", FOCK)
+def test_fock_term_equals_spin_orbital(o, v, naux, seed):
+    """With f_ov != 0 the disconnected triples gain f_IA t_JK^BC (spin-orbital
+    definition); the closed-shell loop folds f_ia t_jk^bc + f_jb t_ik^ac +
+    f_kc t_ij^ab into V."""
+    x = make_inputs(o, v, naux, seed)
+    f = _fock(o, v, seed)
+    e = t_energy(*x.arrays(), fock_ov=f)
+    es = spinorb_t_energy(*x.arrays(), fock_ov=f)
+    assert _rel(e, es) <= 1e-12
+    assert _rel(e, t_energy(*x.arrays())) > 1e-3  # the term is not negligible here
+
+
+def test_zero_fock_is_the_canonical_energy():
+    x = make_inputs(3, 5, 12, 0)
+    assert t_energy(*x.arrays(), fock_ov=np.zeros((3, 5))) == t_energy(*x.arrays())
+
+
+@pytest.mark.parametrize("kind", ["transposed", "sign", "one_term"])
+def test_planted_fock_mistakes_break_the_pin(monkeypatch, kind):
+    x = make_inputs(3, 5, 12, 0)
+    f = _fock(3, 5, 0)
+    ref = spinorb_t_energy(*x.arrays(), fock_ov=f)
+    orig_v = cs.v_tensor
+
+    def v_bad(i, j, k, w, t1, ovov, t2=None, fock_ov=None):
+        v = orig_v(i, j, k, w, t1, ovov)
+        s = -1.0 if kind == "sign" else 1.0
+        tjk = t2[j, k].T if kind == "transposed" else t2[j, k]
+        v += s * fock_ov[i][:, None, None] * tjk[None, :, :]
+        if kind != "one_term":
+            v += s * fock_ov[j][None, :, None] * t2[i, k][:, None, :]
+            v += s * fock_ov[k][None, None, :] * t2[i, j][:, :, None]
+        return v
+    monkeypatch.setattr(cs, "v_tensor", v_bad)
+    assert _rel(cs.t_energy(*x.arrays(), fock_ov=f), ref) > 1e-6
+
+
 # ---------------------------------------------------------------- planted mistakes
 
 def _mutant_x(kind):
@@ -192,7 +239,7 @@ def test_planted_singles_and_weight_mistakes_break_the_pin(monkeypatch):
     ref = spinorb_t_energy(*x.arrays())
     orig_v = cs.v_tensor
 
-    def v_no_singles(i, j, k, w, t1, ovov):
+    def v_no_singles(i, j, k, w, t1, ovov, *rest):
         return w.copy()
     monkeypatch.setattr(cs, "v_tensor", v_no_singles)
     assert _rel(cs.t_energy(*x.arrays()), ref) > 1e-6
