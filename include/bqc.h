@@ -89,6 +89,12 @@ typedef struct {
                                  triple_end <= bqc_t_num_triples(nocc), else BQC_EINVAL.  Shares of
                                  one solve (one per GPU, or consecutive pieces of a long solve) add
                                  up to the whole: every triple's energy does not depend on the range. */
+    const double* fock_ov;    /* NULL: canonical reference (f_ov = 0).  Else f_ia, [nocc][nvir] FP64, host
+                                 or device memory like the other inputs: the occupied-virtual Fock block
+                                 of a reference with diagonal occupied and virtual blocks (orbital
+                                 energies eps); adds the f_ov t2 part of the disconnected triples (paper
+                                 Eqs. 5 and 7: x_k F_ck), folded into V as f_ia t_jk^bc + f_jb t_ik^ac +
+                                 f_kc t_ij^ab.  Must be finite (host) else BQC_EINVAL. */
 } bqc_t_opts;
 
 /* Per-solve measurements.  Times are seconds. */

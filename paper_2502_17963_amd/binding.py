@@ -29,7 +29,8 @@ class TOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("inputs_on_device", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("triple_energies", _dp),
-                ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64)]
+                ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
+                ("fock_ov", _dp)]
 
 
 class TStats(ctypes.Structure):
@@ -156,10 +157,12 @@ def _ptrs(arrays):
 
 def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64",
              device=0, triple_energies=False, timing=False, stream=None, stats=False,
-             triple_range=None):
+             triple_range=None, fock_ov=None):
     """E_T through bqc_t_energy_ex.
 
-    triple_range=(begin, end) solves only that share of the unique triples.
+    triple_range=(begin, end) solves only that share of the unique triples;
+    fock_ov (f_ia, [nocc][nvir], on the same side as the other inputs) adds the
+    f_ov term of a non-canonical reference.
     Returns E_T, or (E_T, extras) when triple_energies or stats is requested;
     extras holds "triples" (numpy array in unique-triple order; with a range,
     entries outside it are zero) and/or "stats".
@@ -173,6 +176,12 @@ def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64
     opts.timing = 1 if timing else 0
     if triple_range is not None:
         opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
+    if fock_ov is not None:
+        fp, f_dev, f_keep = _ptrs((fock_ov,))
+        if f_dev != on_dev:
+            raise ValueError("fock_ov must live where the other inputs live (host or device)")
+        opts.fock_ov = fp[0]
+        keep = list(keep) + list(f_keep)
     if stream is not None:
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:
@@ -197,7 +206,8 @@ def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64
 
 
 def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, precision="fp64",
-                device=0, triple_energies=False, timing=False, stream=None, stats=False, triple_range=None):
+                device=0, triple_energies=False, timing=False, stream=None, stats=False, triple_range=None,
+                fock_ov=None):
     """E_T through bqc_t_energy_df: (ia|bc) formed on the device from the
     density-fitting factors b_ov[naux][nocc][nvir] and b_vv[naux][nvir][nvir].
     Arguments and results as t_energy."""
@@ -210,6 +220,12 @@ def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, 
     opts.timing = 1 if timing else 0
     if triple_range is not None:
         opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
+    if fock_ov is not None:
+        fp, f_dev, f_keep = _ptrs((fock_ov,))
+        if f_dev != on_dev:
+            raise ValueError("fock_ov must live where the other inputs live (host or device)")
+        opts.fock_ov = fp[0]
+        keep = list(keep) + list(f_keep)
     if stream is not None:
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:

@@ -114,6 +114,9 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         return fail(BQC_EINVAL, "density fitting needs naux >= 1 and non-null b_ov, b_vv");
     int rc = validate(o, v, eps_o, eps_v, t1, t2, df ? b_ov : ovvv, ooov, ovov, !dev_in);
     if (rc != BQC_OK) return rc;
+    if (op.fock_ov && !dev_in)
+        for (int64_t a = 0; a < (int64_t)o * v; ++a)
+            if (!std::isfinite(op.fock_ov[a])) return fail(BQC_EINVAL, "non-finite fock_ov element");
     const int64_t ntrip_all = num_triples(o);
     if (op.triple_end == 0 ? op.triple_begin != 0
                            : (op.triple_begin < 0 || op.triple_begin >= op.triple_end || op.triple_end > ntrip_all))
@@ -152,6 +155,7 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     }
     src.push_back(ooov); sizes.push_back((size_t)o * o * o * v);
     src.push_back(ovov); sizes.push_back((size_t)o * v * o * v);
+    if (op.fock_ov) { src.push_back(op.fock_ov); sizes.push_back((size_t)o * v); }
     std::vector<const double*> dst(src.size());
     double upload_s = 0.0;
     size_t in_bytes = 0;
@@ -183,6 +187,7 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     } else {
         in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
     }
+    if (op.fock_ov) in.fock_ov = dst.back();
 
     const Plan plan = make_plan(o, v, op.precision, op.triple_begin, op.triple_end);
     const int64_t nshare = plan.end - plan.begin;

@@ -70,6 +70,7 @@ struct DevInputs {
     int naux = 0;
     double* df_tmp = nullptr;
     int df_block = 0;
+    const double* fock_ov = nullptr;  // f_ia of a non-canonical reference, or nullptr
 };
 
 // Contraction operands in the contraction precision (a1), chunk-major: a
@@ -118,6 +119,8 @@ struct EpiLaunch {
     const double* eps_v;
     const double* t1;
     const double* ovov;
+    const double* t2;      // t2[i][j][a][b] (used with fock_ov)
+    const double* fock_ov; // nullptr: canonical reference; else f_ia [o][v]
     const int4* orbits;    // (A, B, C, |stabiliser|) with A >= B >= C
     int norbit;
     double* partial;       // [ntrip][norbit]

@@ -47,7 +47,11 @@ __device__ __forceinline__ double keep_if(double x, bool keep) {
     return __longlong_as_double(__double_as_longlong(x) & m);
 }
 
-template <typename HT>
+// FOCK: the reference is non-canonical (f_ov != 0) and V also holds
+// f_ia t_jk^bc + f_jb t_ik^ac + f_kc t_ij^ab (paper Eqs. 5 and 7), staged
+// exactly like the singles term (t2 blocks in place of (ov|ov) blocks, f_ov
+// slices in place of t1 slices).
+template <typename HT, bool FOCK>
 __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     const int orb = blockIdx.x, t = blockIdx.y;
     const int4 ob = e.orbits[orb];
@@ -70,6 +74,10 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     // t1s[n][X][x] = t_{i,j,k}^{tile X, x}
     __shared__ double Gs[3][3][3][T2];
     __shared__ double t1s[3][3][T];
+    // f_ov term: Ts[m][X][Y][x][y] with m = 0: t_jk^{bc}, 1: t_ik^{ac}, 2: t_ij^{ab}
+    // (first virtual in tile X, second in Y); fs[n][X][x] = f_{i,j,k}^{tile X, x}
+    __shared__ double Ts[FOCK ? 3 : 1][3][3][FOCK ? T2 : 1];
+    __shared__ double fs[FOCK ? 3 : 1][3][FOCK ? T : 1];
     __shared__ double red[E_THREADS / 64];
 
     const int TT[3] = {ob.x, ob.y, ob.z};  // tile ids 0, 1, 2 -> tiles A, B, C
@@ -96,6 +104,32 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
         // unconditional load at a clamped (valid) index, then masked: no branch
         const double g = e.ovov[((int64_t)p * v + min(x, v - 1)) * ov + (int64_t)q * v + min(y, v - 1)];
         gv[n] = keep_if(g, el < 27 * T2 && x < v && y < v);
+    }
+    // f_ov term loads (same shapes as the singles term)
+    double tv[FOCK ? NG : 1];
+    double fv = 0.0;
+    if constexpr (FOCK) {
+        const int64_t vv = (int64_t)v * v;
+#pragma unroll
+        for (int n = 0; n < NG; ++n) {
+            const int el = threadIdx.x + n * E_THREADS;
+            const int m = el / (9 * T2), rem = el % (9 * T2);
+            const int X = rem / (3 * T2), Y = (rem / T2) % 3, xy = rem % T2;
+            const int tx = X == 0 ? TT[0] : X == 1 ? TT[1] : TT[2];
+            const int ty = Y == 0 ? TT[0] : Y == 1 ? TT[1] : TT[2];
+            const int x = tx * T + xy / T, y = ty * T + xy % T;
+            // m = 0: t_jk^{bc}; 1: t_ik^{ac}; 2: t_ij^{ab}
+            const int p = m == 0 ? j : i, q = m == 2 ? j : k;
+            const double g = e.t2[((int64_t)p * e.o + q) * vv + (int64_t)min(x, v - 1) * v + min(y, v - 1)];
+            tv[n] = keep_if(g, el < 27 * T2 && x < v && y < v);
+        }
+        if (threadIdx.x < 9 * T) {
+            const int n = threadIdx.x / (3 * T), X = (threadIdx.x / T) % 3;
+            const int tx = X == 0 ? TT[0] : X == 1 ? TT[1] : TT[2];
+            const int x = tx * T + threadIdx.x % T;
+            const int on = n == 0 ? i : n == 1 ? j : k;
+            if (x < v) fv = e.fock_ov[(int64_t)on * v + x];
+        }
     }
     double t1v = 0.0;
     if (threadIdx.x < 9 * T) {
@@ -133,6 +167,14 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
         if (el < 27 * T2) (&Gs[0][0][0][0])[el] = gv[n];
     }
     if (threadIdx.x < 9 * T) (&t1s[0][0][0])[threadIdx.x] = t1v;
+    if constexpr (FOCK) {
+#pragma unroll
+        for (int n = 0; n < NG; ++n) {
+            const int el = threadIdx.x + n * E_THREADS;
+            if (el < 27 * T2) (&Ts[0][0][0][0])[el] = tv[n];
+        }
+        if (threadIdx.x < 9 * T) (&fs[0][0][0])[threadIdx.x] = fv;
+    }
 #pragma unroll
     for (int s = 0; s < 6; ++s)
 #pragma unroll
@@ -155,6 +197,9 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
             W[p] = Ws[p][(x * T + y) * T + z];
             V[p] = W[p] + t1s[0][X][x] * Gs[0][Y][Z][y * T + z] + t1s[1][Y][y] * Gs[1][X][Z][x * T + z] +
                    t1s[2][Z][z] * Gs[2][X][Y][x * T + y];
+            if constexpr (FOCK)
+                V[p] += fs[0][X][x] * Ts[0][Y][Z][y * T + z] + fs[1][Y][y] * Ts[1][X][Z][x * T + z] +
+                        fs[2][Z][z] * Ts[2][X][Y][x * T + y];
         }
         const double d = eocc - e.eps_v[a] - e.eps_v[b] - e.eps_v[c];
         const double se = V[0] + V[3] + V[4], so = V[1] + V[2] + V[5];
@@ -237,7 +282,9 @@ __global__ __launch_bounds__(R_THREADS) void reduce_total_kernel(const double* e
 KernelCall epilogue_call(int precision, const EpiLaunch& e) {
     if (e.ntrip > 65535) throw Error(-1, "epilogue batch too large");
     KernelCall k;
-    k.fn = precision == 0 ? (const void*)&epilogue_kernel<double> : (const void*)&epilogue_kernel<float>;
+    const bool f = e.fock_ov != nullptr;
+    k.fn = precision == 0 ? (f ? (const void*)&epilogue_kernel<double, true> : (const void*)&epilogue_kernel<double, false>)
+                          : (f ? (const void*)&epilogue_kernel<float, true> : (const void*)&epilogue_kernel<float, false>);
     k.grid = dim3(e.norbit, e.ntrip);
     k.block = dim3(E_THREADS);
     k.arg(e);

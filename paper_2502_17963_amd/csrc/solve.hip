@@ -135,6 +135,7 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
         EpiLaunch e;
         e.o = o; e.v = v; e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf[k];
         e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
+        e.t2 = in.t2; e.fock_ov = in.fock_ov;
         e.orbits = d_orb; e.norbit = norbit; e.partial = partial;
         return epilogue_call(prec, e);
     };

@@ -95,6 +95,19 @@ def test_density_fitting_argument_checks():
         assert call(10, bad) == (binding.EINVAL, 123.0), k
 
 
+def test_non_finite_fock_rejected():
+    x = make_inputs(3, 5, 10, 0)
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in x.arrays()]
+    f = np.zeros((3, 5))
+    f[1, 2] = np.inf
+    opts = binding.TOpts()
+    opts.fock_ov = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    e = ctypes.c_double(123.0)
+    rc = bqc.lib().bqc_t_energy_ex(3, 5, *ptrs, ctypes.byref(opts), ctypes.byref(e), None)
+    assert rc == binding.EINVAL and e.value == 123.0
+    assert "fock" in bqc.last_error()
+
+
 def test_gap_and_finiteness_checks():
     x = make_inputs(3, 5, 10, 0)
     eo = x.eps_o.copy()
