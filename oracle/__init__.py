@@ -15,8 +15,12 @@ spin_orbital
     A brute-force spin-orbital (T) energy from the textbook definition
     (Raghavachari et al. 1989; Crawford & Schaefer, Rev. Comp. Chem. 14,
     2000), used only on tiny systems to pin the closed-shell oracle.
+mp2
+    The closed-shell MP2 energy (the paper's MP2 equation) with
+    density-fitted integrals, and the spin-orbital MP2 definition that pins
+    it.
 
-Every function works in IEEE FP64.  Parity status: both functions are
+Every function works in IEEE FP64.  Parity status: every function is
 pinned (see tests/test_oracle_pins.py); no function here is "parity
 unpinned".
 """
@@ -28,3 +32,4 @@ from .closed_shell import (  # noqa: F401
     v_tensor,
 )
 from .spin_orbital import spinorb_t_energy  # noqa: F401
+from .mp2 import mp2_energy, pair_energies, spinorb_mp2_energy  # noqa: F401
