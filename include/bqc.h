@@ -146,6 +146,25 @@ int bqc_t_energy_df(int32_t nocc, int32_t nvir, int32_t naux,
                     const double* ooov, const double* ovov,
                     const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats);
 
+/*
+ * Closed-shell MP2 correlation energy with density-fitted integrals (the
+ * paper's MP2 equation; (ia|jb) = sum_Q B^Q_ia B^Q_jb):
+ *   E_MP2 = sum_{ijab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b).
+ * Inputs: eps_o[nocc], eps_v[nvir], b_ov[naux][nocc][nvir] (FP64, row-major),
+ * borrowed.  Of the options only precision (must be BQC_PREC_FP64), device,
+ * inputs_on_device, stream and timing are used (opts may be NULL).  The
+ * integrals are contracted on FP64 MFMA per occupied pair and virtual tile
+ * pair with the denominator applied in registers (no four-index tensor is
+ * stored); the sum is fixed-order and compensated.  Errors: BQC_EINVAL for
+ * sizes < 1, NULL pointers, a non-FP64 precision, non-finite orbital energies
+ * or no gap (max eps_o >= min eps_v); BQC_ENOMEM, BQC_EDEVICE as elsewhere.
+ * stats (may be NULL): gpu_s, total_s, upload_s, flops = nocc(nocc+1)/2 *
+ * 2 nvir^2 naux, footprint_bytes.
+ */
+int bqc_mp2_energy_df(int32_t nocc, int32_t nvir, int32_t naux,
+                      const double* eps_o, const double* eps_v, const double* b_ov,
+                      const bqc_t_opts* opts, double* E_MP2, bqc_t_stats* stats);
+
 /* Number of unique occupied triples for nocc (0 for nocc < 1). */
 int64_t bqc_t_num_triples(int32_t nocc);
 

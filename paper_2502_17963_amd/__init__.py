@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     header_functions,
     last_error,
     lib,
+    mp2_energy_df,
     num_triples,
     t_energy,
     t_energy_df,
@@ -18,4 +19,4 @@ from .binding import (  # noqa: F401
 )
 
 __all__ = ["BqcError", "Server", "PRECISIONS", "footprint", "header_functions", "last_error", "lib",
-           "num_triples", "t_energy", "t_energy_df", "t_energy_plain"]
+           "mp2_energy_df", "num_triples", "t_energy", "t_energy_df", "t_energy_plain"]

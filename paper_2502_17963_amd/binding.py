@@ -88,6 +88,9 @@ def lib():
             L.bqc_t_energy_df.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, *([_dp] * 8),
                                           ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
             L.bqc_t_energy_df.restype = ctypes.c_int
+            L.bqc_mp2_energy_df.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
+                                            ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
+            L.bqc_mp2_energy_df.restype = ctypes.c_int
             L.bqc_t_num_triples.argtypes = [ctypes.c_int32]
             L.bqc_t_num_triples.restype = ctypes.c_int64
             L.bqc_t_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -247,6 +250,26 @@ def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, 
         extras["triples"] = etrip[:num_triples(nocc)]
     extras["stats"] = st.as_dict()
     return e.value, extras
+
+
+def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, stats=False):
+    """E_MP2 through bqc_mp2_energy_df (b_ov[naux][nocc][nvir]; FP64).
+    Returns E_MP2, or (E_MP2, stats dict) with stats=True."""
+    ptrs, on_dev, keep = _ptrs((eps_o, eps_v, b_ov))
+    opts = TOpts()
+    opts.device = device
+    opts.inputs_on_device = 1 if on_dev else 0
+    if stream is not None:
+        opts.stream = ctypes.c_void_p(stream)
+    elif on_dev:
+        import torch
+        opts.stream = ctypes.c_void_p(torch.cuda.current_stream(eps_o.device).cuda_stream)
+    e = ctypes.c_double(0.0)
+    st = TStats()
+    rc = lib().bqc_mp2_energy_df(nocc, nvir, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
+    del keep
+    _check(rc)
+    return (e.value, st.as_dict()) if stats else e.value
 
 
 def t_energy_plain(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov):

@@ -227,6 +227,90 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     return BQC_OK;
 }
 
+// MP2 energy (density-fitted): validation, residency, one enqueue_mp2.
+int mp2_impl(int32_t o, int32_t v, int32_t naux, const double* eps_o, const double* eps_v, const double* b_ov,
+             const bqc_t_opts* opts, double* E, bqc_t_stats* stats) {
+    bqc_t_opts op;
+    std::memset(&op, 0, sizeof(op));
+    if (opts) op = *opts;
+    if (!E) return fail(BQC_EINVAL, "E_MP2 is null");
+    if (o < 1 || v < 1 || naux < 1) return fail(BQC_EINVAL, "nocc, nvir and naux must be >= 1");
+    if (!eps_o || !eps_v || !b_ov) return fail(BQC_EINVAL, "null input pointer");
+    if (op.precision != BQC_PREC_FP64) return fail(BQC_EINVAL, "MP2 runs in FP64 only");
+    const bool dev_in = op.inputs_on_device != 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BQC_EDEVICE, "no HIP device");
+    if (op.device < 0 || op.device >= ndev) return fail(BQC_EINVAL, "device ordinal out of range");
+    auto wall0 = std::chrono::steady_clock::now();
+    DeviceGuard dg(op.device);
+    Ctx* ctx = acquire_ctx(op.device);
+    struct Rel { Ctx* c; ~Rel() { release_ctx(c); } } rel{ctx};
+    if (!ctx->stream) BQC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    if (!ctx->host_energy) BQC_HIP(hipHostMalloc((void**)&ctx->host_energy, 256, hipHostMallocDefault));
+    hipStream_t st = op.stream ? (hipStream_t)op.stream : ctx->stream;
+    std::vector<double> eo(o), ev(v);
+    if (dev_in) {
+        BQC_HIP(hipMemcpyAsync(eo.data(), eps_o, o * sizeof(double), hipMemcpyDeviceToHost, st));
+        BQC_HIP(hipMemcpyAsync(ev.data(), eps_v, v * sizeof(double), hipMemcpyDeviceToHost, st));
+        BQC_HIP(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(eo.data(), eps_o, o * sizeof(double));
+        std::memcpy(ev.data(), eps_v, v * sizeof(double));
+    }
+    double omax = -INFINITY, vmin = INFINITY;
+    for (double x : eo) { if (!std::isfinite(x)) return fail(BQC_EINVAL, "non-finite occupied orbital energy"); omax = std::max(omax, x); }
+    for (double x : ev) { if (!std::isfinite(x)) return fail(BQC_EINVAL, "non-finite virtual orbital energy"); vmin = std::min(vmin, x); }
+    if (!(omax < vmin)) return fail(BQC_EINVAL, "no gap: max eps_o >= min eps_v");
+
+    const double* d_eo = eps_o;
+    const double* d_ev = eps_v;
+    const double* d_b = b_ov;
+    double upload_s = 0.0;
+    size_t in_bytes = 0;
+    if (!dev_in) {
+        const size_t nb = (size_t)naux * o * v;
+        in_bytes = a256(o * sizeof(double)) + a256(v * sizeof(double)) + a256(nb * sizeof(double));
+        ensure(ctx->in, ctx->in_size, in_bytes);
+        char* p = (char*)ctx->in;
+        const auto u0 = std::chrono::steady_clock::now();
+        BQC_HIP(hipMemcpyAsync(p, eps_o, o * sizeof(double), hipMemcpyHostToDevice, st));
+        d_eo = (const double*)p; p += a256(o * sizeof(double));
+        BQC_HIP(hipMemcpyAsync(p, eps_v, v * sizeof(double), hipMemcpyHostToDevice, st));
+        d_ev = (const double*)p; p += a256(v * sizeof(double));
+        BQC_HIP(hipMemcpyAsync(p, b_ov, nb * sizeof(double), hipMemcpyHostToDevice, st));
+        d_b = (const double*)p;
+        BQC_HIP(hipStreamSynchronize(st));
+        upload_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - u0).count();
+    }
+    ensure(ctx->ws, ctx->ws_size, (size_t)mp2_workspace_bytes(o, v));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        BQC_HIP(hipEventCreate(&e0));
+        BQC_HIP(hipEventCreate(&e1));
+        BQC_HIP(hipEventRecord(e0, st));
+    }
+    struct Ev { hipEvent_t a, b; ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); } } evg{e0, e1};
+    double* d_e = enqueue_mp2(o, v, naux, d_eo, d_ev, d_b, ctx->ws, st, nullptr);
+    if (stats) BQC_HIP(hipEventRecord(e1, st));
+    BQC_HIP(hipMemcpyAsync(ctx->host_energy, d_e, sizeof(double), hipMemcpyDeviceToHost, st));
+    BQC_HIP(hipStreamSynchronize(st));
+    const double e = *ctx->host_energy;
+    if (!std::isfinite(e)) return fail(BQC_EDEVICE, "non-finite energy (device arithmetic failed)");
+    *E = e;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        float ms = 0;
+        BQC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        stats->gpu_s = ms * 1e-3;
+        stats->upload_s = upload_s;
+        stats->flops = (double)o * (o + 1) / 2.0 * 2.0 * (double)v * v * naux;
+        stats->footprint_bytes = (uint64_t)mp2_workspace_bytes(o, v) + in_bytes;
+        stats->precision = BQC_PREC_FP64;
+        stats->total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+    }
+    return BQC_OK;
+}
+
 template <typename F>
 int guarded(F&& f) {
     try {
@@ -274,6 +358,11 @@ int bqc_t_energy_df(int32_t nocc, int32_t nvir, int32_t naux, const double* eps_
         return solve_impl(nocc, nvir, eps_o, eps_v, t1, t2, nullptr, ooov, ovov, opts, E_T, stats, true, naux,
                           b_ov, b_vv);
     });
+}
+
+int bqc_mp2_energy_df(int32_t nocc, int32_t nvir, int32_t naux, const double* eps_o, const double* eps_v,
+                      const double* b_ov, const bqc_t_opts* opts, double* E_MP2, bqc_t_stats* stats) {
+    return guarded([&] { return mp2_impl(nocc, nvir, naux, eps_o, eps_v, b_ov, opts, E_MP2, stats); });
 }
 
 int64_t bqc_t_num_triples(int32_t nocc) { return num_triples(nocc); }

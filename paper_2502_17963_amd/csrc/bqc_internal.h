@@ -194,6 +194,13 @@ KernelCall reduce_triples_call(const double* partial, int ntrip, int norbit, con
                                double* e_trip);
 KernelCall reduce_total_call(const double* e_trip, int64_t n, double* out);
 
+// ------------------------------------------------------------------ MP2
+int64_t mp2_workspace_bytes(int o, int v);
+// Enqueues the density-fitted MP2 energy; returns after `st` has drained,
+// with the energy (and the per-pair energies, if pair_e) in the workspace.
+double* enqueue_mp2(int o, int v, int naux, const double* eps_o, const double* eps_v, const double* b_ov,
+                    void* ws, hipStream_t st, double** pair_e);
+
 // ------------------------------------------------------------------ solve
 struct SolveStats {
     double upload_s = 0, prepare_s = 0, gpu_s = 0, gemm_s = 0, epi_s = 0;

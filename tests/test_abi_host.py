@@ -108,6 +108,31 @@ def test_non_finite_fock_rejected():
     assert "fock" in bqc.last_error()
 
 
+def test_mp2_argument_checks():
+    from synth import draw_factors
+    b, eo, ev, _ = draw_factors(3, 5, 10, 0)
+    b_ov = np.ascontiguousarray(b[:, :3, 3:])
+    L = bqc.lib()
+    P = ctypes.POINTER(ctypes.c_double)
+
+    def call(o, v, naux, arrays, precision=0):
+        ptrs = [None if a is None else a.ctypes.data_as(P) for a in arrays]
+        opts = binding.TOpts()
+        opts.precision = precision
+        e = ctypes.c_double(123.0)
+        return L.bqc_mp2_energy_df(o, v, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), None), e.value
+
+    good = [eo, ev, b_ov]
+    for args in [(0, 5, 10), (3, 0, 10), (3, 5, 0)]:
+        assert call(*args, good) == (binding.EINVAL, 123.0)
+    for k in range(3):
+        bad = list(good)
+        bad[k] = None
+        assert call(3, 5, 10, bad) == (binding.EINVAL, 123.0)
+    assert call(3, 5, 10, good, precision=2) == (binding.EINVAL, 123.0)
+    assert "FP64" in bqc.last_error()
+
+
 def test_gap_and_finiteness_checks():
     x = make_inputs(3, 5, 10, 0)
     eo = x.eps_o.copy()
