@@ -145,6 +145,18 @@ def _prec(p):
     return PRECISIONS[p] if isinstance(p, str) else int(p)
 
 
+def _torch_stream(tensor):
+    """Stream handle for device inputs: torch's current stream.  torch's
+    default stream has handle 0, which the ABI reads as "the library's own
+    stream" (not ordered after torch's work), so that stream is synchronised
+    here first."""
+    import torch
+    s = torch.cuda.current_stream(tensor.device)
+    if s.cuda_stream == 0:
+        s.synchronize()
+    return s.cuda_stream
+
+
 def _ptrs(arrays):
     """(pointers, on_device, keepalive) for numpy arrays or torch tensors."""
     first = arrays[0]
@@ -188,8 +200,7 @@ def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64
     if stream is not None:
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:
-        import torch
-        opts.stream = ctypes.c_void_p(torch.cuda.current_stream(arrays[0].device).cuda_stream)
+        opts.stream = ctypes.c_void_p(_torch_stream(arrays[0]))
     etrip = None
     if triple_energies:
         etrip = np.zeros(max(num_triples(nocc), 1))
@@ -232,8 +243,7 @@ def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, 
     if stream is not None:
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:
-        import torch
-        opts.stream = ctypes.c_void_p(torch.cuda.current_stream(arrays[0].device).cuda_stream)
+        opts.stream = ctypes.c_void_p(_torch_stream(arrays[0]))
     etrip = None
     if triple_energies:
         etrip = np.zeros(max(num_triples(nocc), 1))
@@ -262,8 +272,7 @@ def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, s
     if stream is not None:
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:
-        import torch
-        opts.stream = ctypes.c_void_p(torch.cuda.current_stream(eps_o.device).cuda_stream)
+        opts.stream = ctypes.c_void_p(_torch_stream(eps_o))
     e = ctypes.c_double(0.0)
     st = TStats()
     rc = lib().bqc_mp2_energy_df(nocc, nvir, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))

@@ -58,3 +58,19 @@ def test_mp2_no_gap_rejected():
     with pytest.raises(bqc.BqcError) as err:
         bqc.mp2_energy_df(3, 7, 20, eo, ev, b)
     assert "gap" in str(err.value)
+
+
+def test_mp2_device_inputs_right_after_torch_work():
+    """Inputs written by torch on its default stream and passed at once (no
+    caller synchronisation): the binding orders the solve after them."""
+    import torch
+    bqc = _bqc()
+    o, v, naux = 24, 400, 1500
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(5)
+    b = torch.randn((naux, o, v), generator=g, device="cuda:0", dtype=torch.float64) * 0.05
+    eo = torch.sort(torch.rand(o, generator=g, device="cuda:0", dtype=torch.float64) * 1.7 - 2.0).values
+    ev = torch.sort(torch.rand(v, generator=g, device="cuda:0", dtype=torch.float64) * 2.9 + 0.1).values
+    e = bqc.mp2_energy_df(o, v, naux, eo, ev, b)
+    ref = mp2_energy(eo.cpu().numpy(), ev.cpu().numpy(), b.cpu().numpy())
+    assert abs(e - ref) <= 1e-12 * abs(ref)
