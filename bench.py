@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large_fragment",
                     choices=["small", "large_fragment", "precision_sweep", "largest_fragment", "serving",
-                             "copy_calibration"])
+                             "copy_calibration", "mp2"])
     ap.add_argument("--precisions", default="fp32,bf16x3,fp8",
                     help="comma list of candidate contraction precisions for the headline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
@@ -279,6 +279,55 @@ def _run_serving_measurement(args):
             f.write(line + "\n")
 
 
+MP2_SHAPES = [(32, 300, 1000), (48, 480, 1600), (100, 1000, 3000)]
+
+
+def run_mp2(args):
+    """Density-fitted MP2 energy (FP64) at three sizes, factors generated on
+    the GPU; the smallest is also checked against the FP64 oracle."""
+    import torch
+
+    import paper_2502_17963_amd as bqc
+    from oracle.mp2 import mp2_energy
+    from synth import make_mp2_inputs_device
+    recs = []
+    for (o, v, naux) in MP2_SHAPES:
+        eo, ev, b = make_mp2_inputs_device(o, v, naux, 1)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            bqc.mp2_energy_df(o, v, naux, eo, ev, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e, st = bqc.mp2_energy_df(o, v, naux, eo, ev, b, stats=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(args.steps, 1)
+        rec = {"nocc": o, "nvir": v, "naux": naux, "E_MP2": e, "s": round(dt, 5), "gpu_s": round(st["gpu_s"], 5),
+               "tflops": round(st["flops"] / st["gpu_s"] / 1e12, 3), "flops": st["flops"]}
+        if (o, v, naux) == MP2_SHAPES[0]:
+            ref = mp2_energy(eo.cpu().numpy(), ev.cpu().numpy(), b.cpu().numpy())
+            rec["rel_vs_oracle"] = abs(e - ref) / abs(ref)
+        recs.append(rec)
+        print(f"[mp2] o={o} v={v} naux={naux} E={e:.10e} {dt * 1e3:.2f} ms/solve {rec['tflops']} TFLOP/s",
+              file=sys.stderr, flush=True)
+        del eo, ev, b
+        torch.cuda.empty_cache()
+    big = recs[-1]
+    out = {"metric": "MP2 energy (density-fitted) TFLOP/s", "value": big["tflops"], "unit": "TFLOP/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+           "data": "synthetic density-fitting factors generated on the GPU",
+           "config": {"workload": "mp2", "nocc": big["nocc"], "nvir": big["nvir"], "naux": big["naux"]},
+           "roofline": {"bound": "mfma", "achieved": big["tflops"], "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                        "frac": round(big["tflops"] / PEAK_TFLOPS["fp64"], 4), "traffic": None,
+                        "kernel": "mp2_kernel"},
+           "shapes": recs}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
 def run_copy_calibration(args):
     """A plain device copy of known size: the reference for scaling the
     FETCH_SIZE / WRITE_SIZE counters (each launch reads and writes exactly
@@ -299,6 +348,8 @@ def main():
         return run_serving(args)
     if args.workload == "copy_calibration":
         return run_copy_calibration(args)
+    if args.workload == "mp2":
+        return run_mp2(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding of the "
                           "triple blocks is a design note, not implemented"}))

@@ -124,6 +124,25 @@ def make_df_inputs(nocc: int, nvir: int, naux: int, seed: int):
     return (x.eps_o, x.eps_v, x.t1, x.t2, b_ov, b_vv, x.ooov, x.ovov)
 
 
+def make_mp2_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:0"):
+    """Inputs of the density-fitted MP2 energy on a HIP device: (eps_o, eps_v,
+    b_ov[naux][nocc][nvir]) with the distributions of make_inputs (orbital
+    energies as there; b_ov = (X_ov + X_vo^T) / 2, X ~ N(0, 0.05^2), the
+    occupied-virtual block of the symmetrised factor), drawn block-wise so
+    that no (nocc + nvir)^2 factor is formed."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    f64 = torch.float64
+    x_ov = torch.randn((naux, nocc, nvir), generator=g, device=device, dtype=f64) * 0.05
+    x_vo = torch.randn((naux, nvir, nocc), generator=g, device=device, dtype=f64) * 0.05
+    b_ov = (0.5 * (x_ov + x_vo.transpose(1, 2))).contiguous()
+    del x_ov, x_vo
+    eps_o = torch.sort(torch.rand(nocc, generator=g, device=device, dtype=f64) * 1.7 - 2.0).values
+    eps_v = torch.sort(torch.rand(nvir, generator=g, device=device, dtype=f64) * 2.9 + 0.1).values
+    return eps_o.contiguous(), eps_v.contiguous(), b_ov
+
+
 def serving_stream(n_requests: int = 256, seed: int = 4, rate: float | None = None):
     """Fragment shapes for the serving workload.
 
