@@ -216,6 +216,8 @@ def run_serving(args):
     raise SystemExit(SERVING_DISABLED)
 
 
+# The serving measurement (closed loop, alone-vs-mix check, Poisson open
+# loop); unreachable while SERVING_DISABLED holds.
 def _run_serving_measurement(args):
     import numpy as np
     import torch
