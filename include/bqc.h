@@ -95,7 +95,20 @@ typedef struct {
                                  energies eps); adds the f_ov t2 part of the disconnected triples (paper
                                  Eqs. 5 and 7: x_k F_ck), folded into V as f_ia t_jk^bc + f_jb t_ik^ac +
                                  f_kc t_ij^ab.  Must be finite (host) else BQC_EINVAL. */
+    int32_t formulation;      /* BQC_FORM_OCCUPIED (0, default): the loop runs over unique occupied
+                                 triples i <= j <= k with tensors over the virtuals.  BQC_FORM_VIRTUAL:
+                                 the loop runs over unique virtual triples a <= b <= c with tensors over
+                                 the occupied indices (the loop order of paper section 2.4.2); E_T is the
+                                 same sum taken in the other order.  With BQC_FORM_VIRTUAL "triple" in
+                                 triple_energies, triple_begin and triple_end means a unique virtual
+                                 triple (a <= b <= c, lexicographic, a = b = c skipped;
+                                 bqc_t_num_triples(nvir) of them), stats->flops is 12 n_triples nocc^3
+                                 (nocc + nvir), and BQC_PREC_FP8 is rejected with BQC_EINVAL.  Any
+                                 other value: BQC_EINVAL. */
 } bqc_t_opts;
+
+#define BQC_FORM_OCCUPIED 0
+#define BQC_FORM_VIRTUAL  1
 
 /* Per-solve measurements.  Times are seconds. */
 typedef struct {
@@ -165,11 +178,14 @@ int bqc_mp2_energy_df(int32_t nocc, int32_t nvir, int32_t naux,
                       const double* eps_o, const double* eps_v, const double* b_ov,
                       const bqc_t_opts* opts, double* E_MP2, bqc_t_stats* stats);
 
-/* Number of unique occupied triples for nocc (0 for nocc < 1). */
+/* Number of unique triples p <= q <= r (p = q = r excluded) of an orbital
+ * space of n orbitals: the occupied triples for n = nocc, the virtual
+ * triples of BQC_FORM_VIRTUAL for n = nvir (0 for n < 1). */
 int64_t bqc_t_num_triples(int32_t nocc);
 
 /* Device bytes one solve of this shape and precision holds (its footprint,
- * inputs included), or -1 for invalid arguments. */
+ * inputs included) with the default formulation and a canonical reference,
+ * or -1 for invalid arguments. */
 int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision);
 
 /* ---------------------------------------------------------------- serving

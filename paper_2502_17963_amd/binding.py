@@ -30,7 +30,10 @@ class TOpts(ctypes.Structure):
                 ("inputs_on_device", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("triple_energies", _dp),
                 ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
-                ("fock_ov", _dp)]
+                ("fock_ov", _dp), ("formulation", ctypes.c_int32)]
+
+
+FORMULATIONS = {"occupied": 0, "virtual": 1}
 
 
 class TStats(ctypes.Structure):
@@ -170,96 +173,90 @@ def _ptrs(arrays):
     return [ctypes.cast(ctypes.c_void_p(a.data_ptr()), _dp) for a in arrays], True, list(arrays)
 
 
+def _solve_opts(arrays, precision, device, timing, stream, triple_range, fock_ov, formulation):
+    """ctypes options of one solve: (pointers, opts, buffers to keep alive)."""
+    if formulation not in FORMULATIONS:
+        raise ValueError(f"formulation must be one of {sorted(FORMULATIONS)}")
+    ptrs, on_dev, keep = _ptrs(arrays)
+    opts = TOpts()
+    opts.precision = _prec(precision)
+    opts.device = device
+    opts.inputs_on_device = 1 if on_dev else 0
+    opts.timing = 1 if timing else 0
+    opts.formulation = FORMULATIONS[formulation]
+    if triple_range is not None:
+        opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
+    if fock_ov is not None:
+        fp, f_dev, f_keep = _ptrs((fock_ov,))
+        if f_dev != on_dev:
+            raise ValueError("fock_ov must live where the other inputs live (host or device)")
+        opts.fock_ov = fp[0]
+        keep = list(keep) + list(f_keep)
+    if stream is not None:
+        opts.stream = ctypes.c_void_p(stream)
+    elif on_dev:
+        opts.stream = ctypes.c_void_p(_torch_stream(arrays[0]))
+    return ptrs, opts, keep
+
+
+def _finish(rc, e, st, etrip, ntrip, triple_energies, stats, timing):
+    _check(rc)
+    if not (triple_energies or stats or timing):
+        return e.value
+    extras = {}
+    if triple_energies:
+        extras["triples"] = etrip[:ntrip]
+    extras["stats"] = st.as_dict()
+    return e.value, extras
+
+
 def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64",
              device=0, triple_energies=False, timing=False, stream=None, stats=False,
-             triple_range=None, fock_ov=None):
+             triple_range=None, fock_ov=None, formulation="occupied"):
     """E_T through bqc_t_energy_ex.
 
     triple_range=(begin, end) solves only that share of the unique triples;
     fock_ov (f_ia, [nocc][nvir], on the same side as the other inputs) adds the
-    f_ov term of a non-canonical reference.
+    f_ov term of a non-canonical reference; formulation="virtual" runs the
+    loop over unique virtual triples (then "triples" below are those).
     Returns E_T, or (E_T, extras) when triple_energies or stats is requested;
     extras holds "triples" (numpy array in unique-triple order; with a range,
     entries outside it are zero) and/or "stats".
     """
     arrays = (eps_o, eps_v, t1, t2, ovvv, ooov, ovov)
-    ptrs, on_dev, keep = _ptrs(arrays)
-    opts = TOpts()
-    opts.precision = _prec(precision)
-    opts.device = device
-    opts.inputs_on_device = 1 if on_dev else 0
-    opts.timing = 1 if timing else 0
-    if triple_range is not None:
-        opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
-    if fock_ov is not None:
-        fp, f_dev, f_keep = _ptrs((fock_ov,))
-        if f_dev != on_dev:
-            raise ValueError("fock_ov must live where the other inputs live (host or device)")
-        opts.fock_ov = fp[0]
-        keep = list(keep) + list(f_keep)
-    if stream is not None:
-        opts.stream = ctypes.c_void_p(stream)
-    elif on_dev:
-        opts.stream = ctypes.c_void_p(_torch_stream(arrays[0]))
+    ptrs, opts, keep = _solve_opts(arrays, precision, device, timing, stream, triple_range, fock_ov,
+                                   formulation)
+    ntrip = num_triples(nvir if formulation == "virtual" else nocc)
     etrip = None
     if triple_energies:
-        etrip = np.zeros(max(num_triples(nocc), 1))
+        etrip = np.zeros(max(ntrip, 1))
         opts.triple_energies = etrip.ctypes.data_as(_dp)
     e = ctypes.c_double(0.0)
     st = TStats()
     rc = lib().bqc_t_energy_ex(nocc, nvir, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
     del keep
-    _check(rc)
-    if not (triple_energies or stats or timing):
-        return e.value
-    extras = {}
-    if triple_energies:
-        extras["triples"] = etrip[:num_triples(nocc)]
-    extras["stats"] = st.as_dict()
-    return e.value, extras
+    return _finish(rc, e, st, etrip, ntrip, triple_energies, stats, timing)
 
 
 def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, precision="fp64",
                 device=0, triple_energies=False, timing=False, stream=None, stats=False, triple_range=None,
-                fock_ov=None):
+                fock_ov=None, formulation="occupied"):
     """E_T through bqc_t_energy_df: (ia|bc) formed on the device from the
     density-fitting factors b_ov[naux][nocc][nvir] and b_vv[naux][nvir][nvir].
     Arguments and results as t_energy."""
     arrays = (eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov)
-    ptrs, on_dev, keep = _ptrs(arrays)
-    opts = TOpts()
-    opts.precision = _prec(precision)
-    opts.device = device
-    opts.inputs_on_device = 1 if on_dev else 0
-    opts.timing = 1 if timing else 0
-    if triple_range is not None:
-        opts.triple_begin, opts.triple_end = int(triple_range[0]), int(triple_range[1])
-    if fock_ov is not None:
-        fp, f_dev, f_keep = _ptrs((fock_ov,))
-        if f_dev != on_dev:
-            raise ValueError("fock_ov must live where the other inputs live (host or device)")
-        opts.fock_ov = fp[0]
-        keep = list(keep) + list(f_keep)
-    if stream is not None:
-        opts.stream = ctypes.c_void_p(stream)
-    elif on_dev:
-        opts.stream = ctypes.c_void_p(_torch_stream(arrays[0]))
+    ptrs, opts, keep = _solve_opts(arrays, precision, device, timing, stream, triple_range, fock_ov,
+                                   formulation)
+    ntrip = num_triples(nvir if formulation == "virtual" else nocc)
     etrip = None
     if triple_energies:
-        etrip = np.zeros(max(num_triples(nocc), 1))
+        etrip = np.zeros(max(ntrip, 1))
         opts.triple_energies = etrip.ctypes.data_as(_dp)
     e = ctypes.c_double(0.0)
     st = TStats()
     rc = lib().bqc_t_energy_df(nocc, nvir, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
     del keep
-    _check(rc)
-    if not (triple_energies or stats or timing):
-        return e.value
-    extras = {}
-    if triple_energies:
-        extras["triples"] = etrip[:num_triples(nocc)]
-    extras["stats"] = st.as_dict()
-    return e.value, extras
+    return _finish(rc, e, st, etrip, ntrip, triple_energies, stats, timing)
 
 
 def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, stats=False):

@@ -13,8 +13,6 @@
 
 namespace bqc {
 
-double* workspace_etrip(void* ws, int o, int v, int precision);
-double* workspace_energy(void* ws, int o, int v, int precision);
 
 thread_local std::string g_last_error;
 
@@ -109,6 +107,11 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     if (opts) op = *opts;
     if (!E_T) return fail(BQC_EINVAL, "E_T is null");
     if (op.precision < 0 || op.precision > 3) return fail(BQC_EINVAL, "unknown precision");
+    if (op.formulation != BQC_FORM_OCCUPIED && op.formulation != BQC_FORM_VIRTUAL)
+        return fail(BQC_EINVAL, "unknown formulation");
+    const int form = op.formulation == BQC_FORM_VIRTUAL ? FORM_VIR : FORM_OCC;
+    if (form == FORM_VIR && op.precision == BQC_PREC_FP8)
+        return fail(BQC_EINVAL, "the virtual-triple formulation runs in FP64, FP32 or split-BF16x3");
     const bool dev_in = op.inputs_on_device != 0;
     if (df && (naux < 1 || !b_ov || !b_vv))
         return fail(BQC_EINVAL, "density fitting needs naux >= 1 and non-null b_ov, b_vv");
@@ -117,10 +120,10 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     if (op.fock_ov && !dev_in)
         for (int64_t a = 0; a < (int64_t)o * v; ++a)
             if (!std::isfinite(op.fock_ov[a])) return fail(BQC_EINVAL, "non-finite fock_ov element");
-    const int64_t ntrip_all = num_triples(o);
+    const int64_t ntrip_all = num_triples(form == FORM_VIR ? v : o);
     if (op.triple_end == 0 ? op.triple_begin != 0
                            : (op.triple_begin < 0 || op.triple_begin >= op.triple_end || op.triple_end > ntrip_all))
-        return fail(BQC_EINVAL, "triple range outside [0, bqc_t_num_triples(nocc)] or empty");
+        return fail(BQC_EINVAL, "triple range outside [0, number of unique triples] or empty");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BQC_EDEVICE, "no HIP device");
     if (op.device < 0 || op.device >= ndev) return fail(BQC_EINVAL, "device ordinal out of range");
@@ -143,7 +146,6 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         if (rc != BQC_OK) return rc;
     }
 
-    const int64_t ntrip = num_triples(o);
     // inputs: eps_o, eps_v, t1, t2, [ovvv | b_ov, b_vv], ooov, ovov
     std::vector<const double*> src = {eps_o, eps_v, t1, t2};
     std::vector<size_t> sizes = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v};
@@ -189,17 +191,17 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     }
     if (op.fock_ov) in.fock_ov = dst.back();
 
-    const Plan plan = make_plan(o, v, op.precision, op.triple_begin, op.triple_end);
+    const Plan plan = make_plan(o, v, op.precision, op.triple_begin, op.triple_end, form);
     const int64_t nshare = plan.end - plan.begin;
-    ensure(ctx->ws, ctx->ws_size, (size_t)workspace_bytes(o, v, op.precision));
+    ensure(ctx->ws, ctx->ws_size, (size_t)workspace_bytes(o, v, op.precision, form, op.fock_ov != nullptr));
     SolveStats ss;
     enqueue_solve(plan, in, ctx->ws, nullptr, st, ctx->side, op.timing != 0, stats ? &ss : nullptr);
-    BQC_HIP(hipMemcpyAsync(ctx->host_energy, workspace_energy(ctx->ws, o, v, op.precision), sizeof(double),
+    BQC_HIP(hipMemcpyAsync(ctx->host_energy, workspace_energy(ctx->ws, o, v, op.precision, form), sizeof(double),
                            hipMemcpyDeviceToHost, st));
     std::vector<double> etrip;
     if (op.triple_energies && nshare > 0) {
         etrip.resize(nshare);
-        BQC_HIP(hipMemcpyAsync(etrip.data(), workspace_etrip(ctx->ws, o, v, op.precision) + plan.begin,
+        BQC_HIP(hipMemcpyAsync(etrip.data(), workspace_etrip(ctx->ws, o, v, op.precision, form) + plan.begin,
                                nshare * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     BQC_HIP(hipStreamSynchronize(st));
@@ -219,7 +221,9 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         stats->epilogue_launches = ss.epi_launches;
         stats->footprint_bytes = ss.footprint + in_bytes +
                                  (df ? (uint64_t)df_scratch_elems(o, v) * sizeof(double) : 0);
-        stats->flops = 12.0 * (double)nshare * (double)v * v * v * (double)(v + o);
+        // per unique triple: 3 pairs x n planes x n^2 outputs x 2 (2v + 2o), n = tile space
+        const double nt = form == FORM_VIR ? o : v;
+        stats->flops = 12.0 * (double)nshare * nt * nt * nt * (double)(v + o);
         stats->precision = op.precision;
         stats->n_triples = (int32_t)nshare;
         stats->total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();

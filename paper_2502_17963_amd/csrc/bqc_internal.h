@@ -101,15 +101,33 @@ struct Operands {
     int Kv = 0, Ko = 0;
 };
 
+// Formulations of a solve.  FORM_OCC: the loop runs over unique occupied
+// triples i <= j <= k and every launch works on tensors over the virtual
+// indices.  FORM_VIR: the loop runs over unique virtual triples a <= b <= c
+// (the paper's loop order) and the same kernels work on tensors over the
+// occupied indices; the energy is the same sum taken in the other order.
+constexpr int FORM_OCC = 0, FORM_VIR = 1;
+
 // One launch of the contraction kernel covers a batch of triples.
 struct GemmLaunch {
     int o, v;
+    int form;              // FORM_OCC or FORM_VIR (then the triples are virtual and the
+                           // planes, rows and columns of H run over the occupied indices)
     int ntrip;             // triples in the batch
     const int4* trip;      // (i, j, k, m) per triple in the batch
     Operands ops;
     void* hbuf;            // [ntrip][3] pairs of hpair_elems(v) blocked elements in the H precision
 };
 
+// The epilogue is written for triples (i, j, k) of one orbital space and
+// tiles of the other: o is the size of the triples' space and v that of the
+// tiles' space, eps_o / eps_v their orbital energies, t1 [o][v], ovov
+// [o][v][o][v], t2 [o][o][v][v] and fock_ov [o][v] in those roles.  The
+// occupied-triple loop passes the inputs as they are; the virtual-triple loop
+// passes o = nvir, v = nocc, -eps_v, -eps_o and the transposed arrays
+// t1[a][i], (ai|bj), t2[a][b][i][j], f[a][i] (every term of V and of Z is
+// symmetric in the two spaces, and the sign flip keeps D = sum over the
+// triple's energies minus the tiles').
 struct EpiLaunch {
     int o, v;
     int ntrip;
@@ -126,7 +144,8 @@ struct EpiLaunch {
     double* partial;       // [ntrip][norbit]
 };
 
-// Padded contraction lengths and matrix counts of the four factors.
+// Padded contraction lengths and matrix counts of the four factors (the
+// counts of the virtual-triple layout differ, the sizes in bytes do not).
 struct Sizes {
     int Kv, Ko;
     int64_t m_ovvv, m_t2, m_t2l, m_hoo;  // matrices per factor
@@ -180,7 +199,18 @@ struct KernelCall {
 };
 
 void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* ops,
-                    hipStream_t st);
+                    hipStream_t st, int form = FORM_OCC);
+
+// Transposed FP64 inputs of the virtual-triple loop's epilogue (see
+// EpiLaunch), built once per solve: -eps_v, -eps_o, t1[a][i], (ai|bj) as
+// ovov_t[a][i][b][j], and with a non-canonical reference t2[a][b][i][j]
+// and f[a][i].
+struct VirAux {
+    double *neg_eps_v = nullptr, *neg_eps_o = nullptr, *t1_t = nullptr, *ovov_t = nullptr;
+    double *t2_t = nullptr, *fock_t = nullptr;
+};
+int64_t vir_aux_bytes(int o, int v, bool fock);
+VirAux launch_vir_aux(const DevInputs& in, void* aux, hipStream_t st);
 int64_t prepare_bytes(int precision, int o, int v);
 // Occupied planes of (ov|vv) formed per pass of the density-fitting product,
 // and the scratch (doubles) they need.
@@ -188,7 +218,9 @@ int df_block_planes(int o, int v);
 int64_t df_scratch_elems(int o, int v);
 
 KernelCall gemm_call(int precision, const GemmLaunch& g);
-int wave_blocks(int v);  // contraction wave tile (16-blocks per side) used for this v
+// Contraction wave tile (16-blocks per side) for rows and columns of size n;
+// tiles of min_wb .. 5 blocks are considered.
+int wave_blocks(int n, int min_wb = 2);
 KernelCall epilogue_call(int precision, const EpiLaunch& e);
 KernelCall reduce_triples_call(const double* partial, int ntrip, int norbit, const int4* trip,
                                double* e_trip);
@@ -208,23 +240,25 @@ struct SolveStats {
     uint64_t footprint = 0;
 };
 
-// Triple-batch size of a solve: a function of (o, v, precision) only, so
-// that a solve's decomposition never depends on what else runs.
-int batch_triples(int o, int v, int precision);
+// Triple-batch size of a solve: a function of (o, v, precision, form) only,
+// so that a solve's decomposition never depends on what else runs.
+int batch_triples(int o, int v, int precision, int form = FORM_OCC);
 
-// Device bytes a solve holds, excluding its FP64 inputs.
-int64_t workspace_bytes(int o, int v, int precision);
+// Device bytes a solve holds, excluding its FP64 inputs (fock: the solve
+// has an f_ov block, which the virtual-triple loop transposes).
+int64_t workspace_bytes(int o, int v, int precision, int form = FORM_OCC, bool fock = false);
 int64_t input_bytes(int o, int v);
 
 // Host-side plan of a solve: triple table and tile-orbit table.
 struct Plan {
     int o = 0, v = 0, precision = 0, nb = 0;
-    std::vector<int4> trip;    // unique triples (i, j, k, m)
+    int form = FORM_OCC;
+    std::vector<int4> trip;    // unique triples (i, j, k, m) of the loop's orbital space
     std::vector<int4> orbits;  // epilogue tile orbits
     int64_t begin = 0, end = 0;  // the solved share [begin, end) of `trip`
 };
 // Plan of the share [begin, end) of the unique triples (end = 0: all).
-Plan make_plan(int o, int v, int precision, int64_t begin = 0, int64_t end = 0);
+Plan make_plan(int o, int v, int precision, int64_t begin = 0, int64_t end = 0, int form = FORM_OCC);
 
 // A solve whose inputs are resident on the device.  The caller owns `ws`
 // (workspace_bytes(o, v, precision) bytes, 256-byte aligned) and the stream.
@@ -236,6 +270,10 @@ Plan make_plan(int o, int v, int precision, int64_t begin = 0, int64_t end = 0);
 // builds the batch sequence as one hipGraph (kernel nodes with the same
 // dependencies; no stream capture, `side` unused) and launches it on `st` as
 // one unit (no per-kernel timing then).
+// Device pointers of the per-triple energies and of the total in a workspace.
+double* workspace_etrip(void* ws, int o, int v, int precision, int form = FORM_OCC);
+double* workspace_energy(void* ws, int o, int v, int precision, int form = FORM_OCC);
+
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
                    hipStream_t st, hipStream_t side, bool timing, SolveStats* stats, bool graph = false);
 

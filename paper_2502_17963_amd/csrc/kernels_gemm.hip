@@ -17,6 +17,20 @@
 // H_c[c][a][b].  Particle and hole terms therefore run on the same MFMA
 // tiles (K = 2v + 2o per plane).
 //
+// The loop over virtual triples (a, b, c) is the same computation with the
+// two orbital spaces exchanged: with X^{pqr}(x,y,z) = sum_d (xp|qd) t_zy^rd
+// - sum_l (xp|yl) t_lz^qr over occupied x, y, z, the pair of the virtual
+// roles (B middle, A, C) is
+//   H[y][u][w] = X^{ABC}(u, y, w) + X^{CBA}(w, y, u)     (y, u, w occupied)
+//     seg 0 (v): Row = (uA|Bd)        Col = t_{wy}^{Cd}
+//     seg 1 (o): Row = -(uA|yl)       Col = t_{lw}^{BC}
+//     seg 2 (v): Row = t_{uy}^{Ad}    Col = (wC|Bd)
+//     seg 3 (o): Row = t_{lu}^{BA}    Col = -(wC|yl)
+// with (B, A, C) = (a, b, c), (b, a, c), (c, a, b) for the three pairs, so
+// that W^{ijk} = H_a[i][j][k] + H_b[j][i][k] + H_c[k][i][j]: the same
+// kernel with planes, rows and columns over the occupied indices and the
+// operand matrices of the virtual-triple layout (FORM = 1).
+//
 // Work decomposition: one work group = one plane y of one pair of one
 // triple, and a tile of up to 160 x 160 (u, w).  The 16-row blocks of v are
 // split evenly over the tiles (v = 300: 19 blocks -> 10 + 9), and each of the
@@ -138,6 +152,36 @@ __device__ __forceinline__ SegGeom seg_geom(int s, int o, int v, int nch_v, int 
     return g;
 }
 
+// The same for the loop over virtual triples: q = B, P = A, R = C (virtual),
+// y the occupied plane; matrices of the virtual-triple layout (bqc_internal.h).
+__device__ __forceinline__ SegGeom seg_geom_vir(int s, int v, int nch_v, int nch_o, int B, int A, int C,
+                                                int y) {
+    SegGeom g;
+    switch (s) {
+        case 0:  // Row (uA|Bd): ovvv[A*v+B]     Col t_wy^Cd: t2[y*v+C]
+            g.row_mat = (int64_t)A * v + B; g.arr_row = 0;
+            g.col_mat = (int64_t)y * v + C; g.arr_col = 1;
+            g.nchunk = nch_v;
+            break;
+        case 1:  // Row -(uA|yl): hoo[y*v+A]     Col t_lw^BC: t2l[B*v+C]
+            g.row_mat = (int64_t)y * v + A; g.arr_row = 3;
+            g.col_mat = (int64_t)B * v + C; g.arr_col = 2;
+            g.nchunk = nch_o;
+            break;
+        case 2:  // Row t_uy^Ad: t2[y*v+A]       Col (wC|Bd): ovvv[C*v+B]
+            g.row_mat = (int64_t)y * v + A; g.arr_row = 1;
+            g.col_mat = (int64_t)C * v + B; g.arr_col = 0;
+            g.nchunk = nch_v;
+            break;
+        default:  // Row t_lu^BA: t2l[B*v+A]     Col -(wC|yl): hoo[y*v+C]
+            g.row_mat = (int64_t)B * v + A; g.arr_row = 2;
+            g.col_mat = (int64_t)y * v + C; g.arr_col = 3;
+            g.nchunk = nch_o;
+            break;
+    }
+    return g;
+}
+
 __device__ __forceinline__ const char* arr_base(const Operands& ops, int a) {
     const void* p = a == 0 ? ops.ovvv : a == 1 ? ops.t2 : a == 2 ? ops.t2l : ops.hoo;
     return (const char*)p;
@@ -152,7 +196,7 @@ __device__ __forceinline__ void roles(int h, int i, int j, int k, int& q, int& P
     else { q = k; P = i; R = j; }
 }
 
-template <int PREC, class G>
+template <int PREC, class G, int FORM>
 __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile_u,
                                                               int ntile_w, int per_xcd) {
     constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, NVEC = G::NVEC, WB = G::WB;
@@ -162,20 +206,22 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
     typedef typename M::HT HT;
     constexpr int KC = M::KC;
 
-    // XCD-aware order: hardware block n runs on XCD n % 8; each XCD gets a
+    // XCD-aware order: hardware block hw runs on XCD hw % 8; each XCD gets a
     // contiguous range of logical tiles (neighbours share operands in L2).
-    const int n = blockIdx.x;
-    const int L = (n % 8) * per_xcd + n / 8;
+    const int hw = blockIdx.x;
+    const int L = (hw % 8) * per_xcd + hw / 8;
     if (L >= n_wg) return;
     const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
+    // size of the space the planes, rows and columns of H run over
+    const int n = FORM == FORM_VIR ? o : v;
     int rem = L;
     const int tw = rem % ntile_w; rem /= ntile_w;
     const int tu = rem % ntile_u; rem /= ntile_u;
     // the three pairs of a plane are neighbours: they share the plane's
     // (ov|vv) rows of i, j and k in L2 (half the HBM fetch of pair-major order)
     const int h = rem % 3; rem /= 3;
-    const int y = rem % v;
-    const int t = rem / v;
+    const int y = rem % n;
+    const int t = rem / n;
     const int4 tr = g.trip[t];
     int q, P, R;
     roles(h, tr.x, tr.y, tr.z, q, P, R);
@@ -215,7 +261,7 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
         isrow[e] = row < TILE_U;
         const int r = isrow[e] ? row : row - TILE_U;
         const int gr = (isrow[e] ? ub : wb) * 16 + r;
-        ok[e] = row < NROW && r < (isrow[e] ? un : wn) * 16 && gr < v;
+        ok[e] = row < NROW && r < (isrow[e] ? un : wn) * 16 && gr < n;
         off[e] = gr * ROWB + qv * 16;
     }
 
@@ -227,7 +273,7 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
         else if (c < 2 * nch_v + nch_o) { s = 2; kb = c - nch_v - nch_o; }
         else { s = 3; kb = c - 2 * nch_v - nch_o; }
     };
-    const int64_t blk = (int64_t)v * ROWB;  // bytes of one chunk block (all v rows)
+    const int64_t blk = (int64_t)n * ROWB;  // bytes of one chunk block (all n rows)
 
     // FP8 scale words: thread tid stages rows tid and tid + 256 (< NROW)
     constexpr int NSROW = (NROW + NTHR - 1) / NTHR;
@@ -240,7 +286,7 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
             const bool isr = row < TILE_U;
             const int r = isr ? row : row - TILE_U;
             const int gr = (isr ? ub : wb) * 16 + r;
-            srow_ok[e] = row < NROW && r < (isr ? un : wn) * 16 && gr < v;
+            srow_ok[e] = row < NROW && r < (isr ? un : wn) * 16 && gr < n;
             srow_g[e] = gr;
         }
     }
@@ -250,7 +296,8 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
     auto load = [&](int c) {
         int s, kb;
         chunk_seg(c, s, kb);
-        const SegGeom sg = seg_geom(s, o, v, nch_v, nch_o, q, P, R, y);
+        const SegGeom sg = FORM == FORM_VIR ? seg_geom_vir(s, v, nch_v, nch_o, q, P, R, y)
+                                            : seg_geom(s, o, v, nch_v, nch_o, q, P, R, y);
         const char* rb = arr_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * blk;
         const char* cb = arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * blk;
 #pragma unroll
@@ -259,8 +306,8 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
             reg[e] = ok[e] ? *(const u4*)(base + off[e]) : u4{0, 0, 0, 0};
         }
         if constexpr (PREC == 3) {
-            const uint32_t* rs = scale_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * (int64_t)v;
-            const uint32_t* cs = scale_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * (int64_t)v;
+            const uint32_t* rs = scale_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * (int64_t)n;
+            const uint32_t* cs = scale_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * (int64_t)n;
 #pragma unroll
             for (int e = 0; e < NSROW; ++e) {
                 const int row = tid + e * NTHR;
@@ -383,8 +430,8 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
     }
 
     // H in EPI_T^3 blocks (layout in bqc_internal.h)
-    const int nt = ceil_div(v, EPI_T);
-    HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(v) +
+    const int nt = ceil_div(n, EPI_T);
+    HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(n) +
               (int64_t)(y >> 3) * nt * nt * 512 + (y & 7) * 64;
     const int u00 = (ub + wub) * 16, w00 = (wb + wwb) * 16;
 #pragma unroll
@@ -397,7 +444,7 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int u = u00 + m * 16 + M::row(lane, r);
-                    if (u < v && w < v) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
+                    if (u < n && w < n) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
                 }
             }
 }
@@ -406,16 +453,17 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
 
 namespace {
 
-template <int PREC, class G>
+template <int PREC, class G, int FORM>
 KernelCall geo_call(const GemmLaunch& g) {
-    const int nblk = ceil_div(g.v, 16);
+    const int n = FORM == FORM_VIR ? g.o : g.v;
+    const int nblk = ceil_div(n, 16);
     const int ntile_u = ceil_div(nblk, G::WU * G::WB), ntile_w = ceil_div(nblk, G::WW * G::WB);
-    const int64_t n64 = (int64_t)g.ntrip * 3 * g.v * ntile_u * ntile_w;
+    const int64_t n64 = (int64_t)g.ntrip * 3 * n * ntile_u * ntile_w;
     if (n64 > ((int64_t)1 << 31) - 8) throw Error(-1, "contraction grid too large");
     const int n_wg = (int)n64;
     const int per_xcd = ceil_div(n_wg, 8);
     KernelCall k;
-    k.fn = (const void*)&h_gemm_kernel<PREC, G>;
+    k.fn = (const void*)&h_gemm_kernel<PREC, G, FORM>;
     k.grid = dim3(per_xcd * 8);
     k.block = dim3(G::NTHR);
     k.arg(g).arg(n_wg).arg(nblk).arg(ntile_u).arg(ntile_w).arg(per_xcd);
@@ -432,24 +480,39 @@ double block_use(int nblk, int wb) {
 
 template <int PREC>
 KernelCall mode_call(const GemmLaunch& g) {
+    if (g.form == FORM_VIR) {
+        // occupied spaces are small: tiles down to one 16 x 16 block per wave
+        if constexpr (PREC == 3) {
+            throw Error(-1, "the virtual-triple loop has no FP8 contraction");
+        } else {
+            switch (wave_blocks(g.o, 1)) {
+                case 1: return geo_call<PREC, Geo<2, 2, 1>, FORM_VIR>(g);
+                case 2: return geo_call<PREC, Geo<2, 2, 2>, FORM_VIR>(g);
+                case 3: return geo_call<PREC, Geo<2, 2, 3>, FORM_VIR>(g);
+                case 4: return geo_call<PREC, Geo<2, 2, 4>, FORM_VIR>(g);
+                default: return geo_call<PREC, Geo<2, 2, 5>, FORM_VIR>(g);
+            }
+        }
+    }
     switch (wave_blocks(g.v)) {
-        case 2: return geo_call<PREC, Geo<2, 2, 2>>(g);
-        case 3: return geo_call<PREC, Geo<2, 2, 3>>(g);
-        case 4: return geo_call<PREC, Geo<2, 2, 4>>(g);
-        default: return geo_call<PREC, Geo<2, 2, 5>>(g);
+        case 2: return geo_call<PREC, Geo<2, 2, 2>, FORM_OCC>(g);
+        case 3: return geo_call<PREC, Geo<2, 2, 3>, FORM_OCC>(g);
+        case 4: return geo_call<PREC, Geo<2, 2, 4>, FORM_OCC>(g);
+        default: return geo_call<PREC, Geo<2, 2, 5>, FORM_OCC>(g);
     }
 }
 
 }  // namespace
 
-// Wave tile size (blocks per side) for this v: a smaller tile wastes fewer
-// block products on partial tiles but loads more operand bytes per flop, so
-// it is taken only when its useful share is at least 20% higher.
-int wave_blocks(int v) {
-    const int nblk = ceil_div(v, 16);
+// Wave tile size (blocks per side) for rows and columns of size n: a smaller
+// tile wastes fewer block products on partial tiles but loads more operand
+// bytes per flop, so it is taken only when its useful share is at least 20%
+// higher.
+int wave_blocks(int n, int min_wb) {
+    const int nblk = ceil_div(n, 16);
     int best = 5;
     double use = block_use(nblk, 5);
-    for (int wb = 4; wb >= 2; --wb) {
+    for (int wb = 4; wb >= min_wb; --wb) {
         const double u = block_use(nblk, wb);
         if (u > 1.2 * use) { use = u; best = wb; }
     }

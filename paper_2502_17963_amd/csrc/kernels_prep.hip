@@ -13,6 +13,13 @@
 //   t2_c    M = P*o + q:  r = u, k = d   t_Pq^ud
 //   t2l_c   M = P*v + y:  r = u, k = l   t_lP^yu = t2[l][P][y][u]
 //   hoo_c   M = q*o + P:  r = u, k = l   -(Pu|ql) = -ooov[q][l][P][u]
+// The loop over virtual triples uses the same four factors with the two
+// orbital spaces exchanged: matrices of o rows (occupied u or w),
+//   ovvv_c  M = A*v + B:  r = u, k = d   (uA|Bd)       = ovvv[u][A][B][d]
+//   t2_c    M = y*v + A:  r = u, k = d   t_uy^Ad       = t2[u][y][A][d]
+//   t2l_c   M = B*v + C:  r = w, k = l   t_lw^BC       = t2[l][w][B][C]
+//   hoo_c   M = y*v + A:  r = u, k = l   -(uA|yl)      = -ooov[y][l][u][A]
+// (the same element counts as the occupied-triple layout).
 // KC = elements per 128-byte chunk: 16 (FP64), 32 (FP32), and for the
 // split-BF16x3 mode a chunk holds 32 bf16 hi parts followed by their 32 lo
 // parts (x_hi = bf16(x), x_lo = bf16(x - x_hi)).  The FP8 mode pads to 128
@@ -57,7 +64,8 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 __device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // Source value of factor F at (matrix M, row r, contraction index k < len).
-enum Factor { F_OVVV = 0, F_T2 = 1, F_T2L = 2, F_HOO = 3 };
+// F_V_*: the factors of the virtual-triple layout.
+enum Factor { F_OVVV = 0, F_T2 = 1, F_T2L = 2, F_HOO = 3, F_V_OVVV = 4, F_V_T2 = 5, F_V_T2L = 6, F_V_HOO = 7 };
 
 template <int F>
 __device__ __forceinline__ double source(const double* __restrict__ src, int64_t M, int64_t r, int64_t k,
@@ -69,35 +77,52 @@ __device__ __forceinline__ double source(const double* __restrict__ src, int64_t
         return src[(M * v + r) * v + k];
     } else if constexpr (F == F_T2L) {  // t2[l][P][y][u]
         return src[k * o * v * v + M * v + r];
-    } else {  // -ooov[q][l][P][u]
+    } else if constexpr (F == F_HOO) {  // -ooov[q][l][P][u]
         const int64_t q = M / o, P = M % o;
         return -src[((q * o + k) * o + P) * v + r];
+    } else if constexpr (F == F_V_OVVV) {  // ovvv[u][A][B][d], M = A v + B (src may start at a row block)
+        return src[r * v * v * v + M * v + k];
+    } else if constexpr (F == F_V_T2) {  // t2[u][y][A][d], M = y v + A
+        return src[r * o * v * v + M * v + k];
+    } else if constexpr (F == F_V_T2L) {  // t2[l][w][B][C], M = B v + C
+        return src[(k * o + r) * v * v + M];
+    } else {  // -ooov[y][l][u][A], M = y v + A
+        const int64_t y = M / v, A = M % v;
+        return -src[((y * o + k) * o + r) * v + A];
     }
 }
 
-// One thread per destination element (chunk-major order).
+// Rows of every matrix of factor F: v in the occupied-triple layout, o in
+// the virtual-triple layout.
+template <int F>
+constexpr bool vir_factor() { return F >= F_V_OVVV; }
+
+// One thread per destination element (chunk-major order) of the rows
+// [row0, row0 + nrows) of every matrix (matrices of `rows` rows); the
+// source is read at the row relative to row0.
 template <int PREC, int F>
-__global__ void make_factor(const double* __restrict__ src, void* dst, int64_t nmat, int len, int kpad,
-                            int o, int v) {
+__global__ void make_factor(const double* __restrict__ src, void* dst, int64_t nmat, int rows, int row0,
+                            int nrows, int len, int kpad, int o, int v) {
     constexpr int KC = (PREC == 0) ? 16 : 32;
     const int nchunk = kpad / KC;
-    const int64_t n = nmat * nchunk * (int64_t)v * KC;
+    const int64_t n = nmat * nchunk * (int64_t)nrows * KC;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int kk = (int)(idx % KC);
         int64_t rest = idx / KC;
-        const int64_t r = rest % v; rest /= v;
+        const int64_t r = rest % nrows; rest /= nrows;
         const int c = (int)(rest % nchunk);
         const int64_t M = rest / nchunk;
         const int k = c * KC + kk;
         const double x = k < len ? source<F>(src, M, r, k, o, v) : 0.0;
+        const int64_t di = (((M * nchunk + c) * rows) + row0 + r) * KC + kk;  // destination element
         if constexpr (PREC == 0) {
-            ((double*)dst)[idx] = x;
+            ((double*)dst)[di] = x;
         } else if constexpr (PREC == 1) {
-            ((float*)dst)[idx] = (float)x;
+            ((float*)dst)[di] = (float)x;
         } else {
             // chunk of 32 elements -> 32 hi parts then 32 lo parts
-            uint16_t* d = (uint16_t*)dst + (idx - kk) * 2;
+            uint16_t* d = (uint16_t*)dst + (di - kk) * 2;
             const uint16_t h = bf16_bits((float)x);
             d[kk] = h;
             d[32 + kk] = bf16_bits((float)(x - (double)bf16_value(h)));
@@ -275,10 +300,47 @@ namespace {
 
 template <int PREC, int F>
 void launch_factor(const double* src, void* dst, int64_t nmat, int len, int kpad, int o, int v,
-                   hipStream_t st) {
-    const int64_t n = nmat * (int64_t)v * kpad;
-    hipLaunchKernelGGL((make_factor<PREC, F>), grid_for(n), dim3(P_THREADS), 0, st, src, dst, nmat, len, kpad,
-                       o, v);
+                   hipStream_t st, int row0 = 0, int nrows = -1) {
+    const int rows = vir_factor<F>() ? o : v;
+    if (nrows < 0) nrows = rows;
+    const int64_t n = nmat * (int64_t)nrows * kpad;
+    hipLaunchKernelGGL((make_factor<PREC, F>), grid_for(n), dim3(P_THREADS), 0, st, src, dst, nmat, rows, row0,
+                       nrows, len, kpad, o, v);
+}
+
+// The factors of the virtual-triple layout (same byte sizes and order as
+// those of prepare_t); with density fitting, (uA|Bd) is formed for a block
+// of occupied u at a time and written to those rows of every matrix.
+template <int PREC>
+void prepare_vir(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
+    const int o = in.o, v = in.v;
+    const Sizes z = factor_sizes(o, v, PREC);
+    const int eb = operand_bytes(PREC);
+    const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v;
+    char* p = (char*)ws;
+    void* d_ovvv = p; p += align256((size_t)vv * o * z.Kv * eb);
+    void* d_t2 = p;   p += align256((size_t)ov * o * z.Kv * eb);
+    void* d_t2l = p;  p += align256((size_t)vv * o * z.Ko * eb);
+    void* d_hoo = p;
+    if (in.ovvv) {
+        launch_factor<PREC, F_V_OVVV>(in.ovvv, d_ovvv, vv, v, z.Kv, o, v, st);
+    } else {
+        for (int P0 = 0; P0 < o; P0 += in.df_block) {
+            const int np = std::min(in.df_block, o - P0);
+            launch_df_ovvv(in, P0, np, st);
+            launch_factor<PREC, F_V_OVVV>(in.df_tmp, d_ovvv, vv, v, z.Kv, o, v, st, P0, np);
+        }
+    }
+    launch_factor<PREC, F_V_T2>(in.t2, d_t2, ov, v, z.Kv, o, v, st);
+    launch_factor<PREC, F_V_T2L>(in.t2, d_t2l, vv, o, z.Ko, o, v, st);
+    launch_factor<PREC, F_V_HOO>(in.ooov, d_hoo, ov, o, z.Ko, o, v, st);
+    BQC_HIP(hipGetLastError());
+    ops->ovvv = d_ovvv;
+    ops->t2 = d_t2;
+    ops->t2l = d_t2l;
+    ops->hoo = d_hoo;
+    ops->Kv = z.Kv;
+    ops->Ko = z.Ko;
 }
 
 template <int PREC>
@@ -361,7 +423,15 @@ int64_t prepare_bytes(int precision, int o, int v) {
     return b;
 }
 
-void launch_prepare(int precision, const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
+void launch_prepare(int precision, const DevInputs& in, void* ws, Operands* ops, hipStream_t st, int form) {
+    if (form == FORM_VIR) {
+        switch (precision) {
+            case 0: prepare_vir<0>(in, ws, ops, st); return;
+            case 1: prepare_vir<1>(in, ws, ops, st); return;
+            case 2: prepare_vir<2>(in, ws, ops, st); return;
+            default: throw Error(-1, "the virtual-triple loop runs in FP64, FP32 or split-BF16x3");
+        }
+    }
     switch (precision) {
         case 0: prepare_t<0>(in, ws, ops, st); break;
         case 1: prepare_t<1>(in, ws, ops, st); break;
@@ -369,6 +439,78 @@ void launch_prepare(int precision, const DevInputs& in, void* ws, Operands* ops,
         case 3: prepare_fp8(in, ws, ops, st); break;
         default: throw Error(-1, "unknown precision");
     }
+}
+
+// ------------------------------------------------------------------ virtual-triple epilogue inputs
+namespace {
+
+// dst[e] for e < n: the transposes of the epilogue's inputs (one thread per
+// destination element).  kind 0: dst[a][i] = src[i][a] (t1, f_ov; o x v
+// source); 1: dst[a][i][b][j] = src[i][a][j][b] ((ia|jb)); 2: dst[a][b][i][j]
+// = src[i][j][a][b] (t2); 3: dst[x] = -src[x].
+__global__ void vir_aux_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int kind,
+                               int o, int v) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t si;
+        if (kind == 0) {
+            const int64_t a = e / o, i = e % o;
+            si = i * v + a;
+        } else if (kind == 1) {
+            int64_t r = e;
+            const int64_t j = r % o; r /= o;
+            const int64_t b = r % v; r /= v;
+            const int64_t i = r % o;
+            const int64_t a = r / o;
+            si = ((i * v + a) * o + j) * v + b;
+        } else if (kind == 2) {
+            int64_t r = e;
+            const int64_t j = r % o; r /= o;
+            const int64_t i = r % o; r /= o;
+            const int64_t b = r % v;
+            const int64_t a = r / v;
+            si = ((i * o + j) * v + a) * v + b;
+        } else {
+            dst[e] = -src[e];
+            continue;
+        }
+        dst[e] = src[si];
+    }
+}
+
+void launch_aux(const double* src, double* dst, int64_t n, int kind, int o, int v, hipStream_t st) {
+    hipLaunchKernelGGL(vir_aux_kernel, grid_for(n), dim3(P_THREADS), 0, st, src, dst, n, kind, o, v);
+    BQC_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+int64_t vir_aux_bytes(int o, int v, bool fock) {
+    const int64_t ov = (int64_t)o * v;
+    int64_t b = align256(v * 8) + align256(o * 8) + align256(ov * 8) + align256(ov * ov * 8);
+    if (fock) b += align256(ov * ov * 8) + align256(ov * 8);
+    return b;
+}
+
+VirAux launch_vir_aux(const DevInputs& in, void* aux, hipStream_t st) {
+    const int o = in.o, v = in.v;
+    const int64_t ov = (int64_t)o * v;
+    char* p = (char*)aux;
+    VirAux x;
+    x.neg_eps_v = (double*)p; p += align256(v * 8);
+    x.neg_eps_o = (double*)p; p += align256(o * 8);
+    x.t1_t = (double*)p;      p += align256(ov * 8);
+    x.ovov_t = (double*)p;    p += align256(ov * ov * 8);
+    launch_aux(in.eps_v, x.neg_eps_v, v, 3, o, v, st);
+    launch_aux(in.eps_o, x.neg_eps_o, o, 3, o, v, st);
+    launch_aux(in.t1, x.t1_t, ov, 0, o, v, st);
+    launch_aux(in.ovov, x.ovov_t, ov * ov, 1, o, v, st);
+    if (in.fock_ov) {
+        x.t2_t = (double*)p;   p += align256(ov * ov * 8);
+        x.fock_t = (double*)p;
+        launch_aux(in.t2, x.t2_t, ov * ov, 2, o, v, st);
+        launch_aux(in.fock_ov, x.fock_t, ov, 0, o, v, st);
+    }
+    return x;
 }
 
 }  // namespace bqc

@@ -38,7 +38,6 @@ int fail(int code, const std::string& msg);
 int validate(int32_t nocc, int32_t nvir, const double* eps_o, const double* eps_v, const double* t1,
              const double* t2, const double* ovvv, const double* ooov, const double* ovov,
              bool host_eps);
-double* workspace_energy(void* ws, int o, int v, int precision);
 
 namespace {
 

@@ -2,6 +2,10 @@
 // workspace layout and the launch sequence
 //   prepare (a1) -> per triple batch: contraction, epilogue, per-triple sum
 //   -> compensated sum over triples.
+// The loop runs over unique occupied triples with tiles of virtuals
+// (FORM_OCC), or over unique virtual triples with tiles of occupied indices
+// (FORM_VIR, the paper's loop order); "triple space" and "tile space" below
+// are (occupied, virtual) or (virtual, occupied) accordingly.
 #include <algorithm>
 #include <chrono>
 
@@ -17,15 +21,19 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int64_t kHBudget = (int64_t)1 << 30;
 
 struct Layout {
-    size_t ops, trip, orbits, hbuf, partial, etrip, energy, total;
+    size_t ops, trip, orbits, hbuf, partial, etrip, energy, aux, total;
 };
 
-Layout layout(int o, int v, int precision) {
-    const int nb = batch_triples(o, v, precision);
-    const int nt = ceil_div(v, EPI_T);
+// sizes of the triple space and of the tile space
+inline int triple_space(int o, int v, int form) { return form == FORM_VIR ? v : o; }
+inline int tile_space(int o, int v, int form) { return form == FORM_VIR ? o : v; }
+
+Layout layout(int o, int v, int precision, int form, bool fock) {
+    const int nb = batch_triples(o, v, precision, form);
+    const int nt = ceil_div(tile_space(o, v, form), EPI_T);
     const int64_t norbit = num_tile_orbits(nt);
-    const int64_t ntrip = num_triples(o);
-    const int64_t hp = hpair_elems(v);
+    const int64_t ntrip = num_triples(triple_space(o, v, form));
+    const int64_t hp = hpair_elems(tile_space(o, v, form));
     Layout L;
     size_t off = 0;
     L.ops = off; off += align256(prepare_bytes(precision, o, v));
@@ -35,22 +43,25 @@ Layout layout(int o, int v, int precision) {
     L.partial = off; off += align256((size_t)nb * norbit * sizeof(double));
     L.etrip = off; off += align256((size_t)std::max<int64_t>(ntrip, 1) * sizeof(double));
     L.energy = off; off += 256;
+    L.aux = off; off += form == FORM_VIR ? align256(vir_aux_bytes(o, v, fock)) : 0;
     L.total = off;
     return L;
 }
 
 }  // namespace
 
-int batch_triples(int o, int v, int precision) {
-    const int64_t per = 3 * hpair_elems(v) * hbuf_bytes(precision);
+int batch_triples(int o, int v, int precision, int form) {
+    const int64_t per = 3 * hpair_elems(tile_space(o, v, form)) * hbuf_bytes(precision);
     int64_t nb = kHBudget / std::max<int64_t>(per, 1);
     nb = std::max<int64_t>(nb, 1);
-    nb = std::min<int64_t>(nb, std::max<int64_t>(num_triples(o), 1));
+    nb = std::min<int64_t>(nb, std::max<int64_t>(num_triples(triple_space(o, v, form)), 1));
     nb = std::min<int64_t>(nb, 4096);
     return (int)nb;
 }
 
-int64_t workspace_bytes(int o, int v, int precision) { return (int64_t)layout(o, v, precision).total; }
+int64_t workspace_bytes(int o, int v, int precision, int form, bool fock) {
+    return (int64_t)layout(o, v, precision, form, fock).total;
+}
 
 int64_t input_bytes(int o, int v) {
     const int64_t n = (int64_t)o + v + (int64_t)o * v + (int64_t)o * o * v * v +
@@ -58,22 +69,24 @@ int64_t input_bytes(int o, int v) {
     return n * 8 + 7 * 256;
 }
 
-Plan make_plan(int o, int v, int precision, int64_t begin, int64_t end) {
+Plan make_plan(int o, int v, int precision, int64_t begin, int64_t end, int form) {
     Plan p;
     p.o = o;
     p.v = v;
     p.precision = precision;
-    p.nb = batch_triples(o, v, precision);
-    for (int i = 0; i < o; ++i)
-        for (int j = i; j < o; ++j)
-            for (int k = j; k < o; ++k) {
+    p.form = form;
+    p.nb = batch_triples(o, v, precision, form);
+    const int nx = triple_space(o, v, form);
+    for (int i = 0; i < nx; ++i)
+        for (int j = i; j < nx; ++j)
+            for (int k = j; k < nx; ++k) {
                 if (i == j && j == k) continue;
                 const int m = (i < j && j < k) ? 6 : 3;
                 p.trip.push_back(make_int4(i, j, k, m));
             }
     p.begin = end > 0 ? begin : 0;
     p.end = end > 0 ? end : (int64_t)p.trip.size();
-    const int nt = ceil_div(v, EPI_T);
+    const int nt = ceil_div(tile_space(o, v, form), EPI_T);
     for (int A = 0; A < nt; ++A)
         for (int B = 0; B <= A; ++B)
             for (int C = 0; C <= B; ++C) {
@@ -85,12 +98,12 @@ Plan make_plan(int o, int v, int precision, int64_t begin, int64_t end) {
 
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
                    hipStream_t st, hipStream_t side, bool timing, SolveStats* stats, bool graph) {
-    const int o = plan.o, v = plan.v, prec = plan.precision;
-    const Layout L = layout(o, v, prec);
+    const int o = plan.o, v = plan.v, prec = plan.precision, form = plan.form;
+    const Layout L = layout(o, v, prec, form, in.fock_ov != nullptr);
     char* base = (char*)ws;
     int4* d_trip = (int4*)(base + L.trip);
     int4* d_orb = (int4*)(base + L.orbits);
-    const size_t hsize = (size_t)plan.nb * 3 * hpair_elems(v) * hbuf_bytes(prec);
+    const size_t hsize = (size_t)plan.nb * 3 * hpair_elems(tile_space(o, v, form)) * hbuf_bytes(prec);
     void* hbuf[2] = {base + L.hbuf, base + L.hbuf + align256(hsize)};
     double* partial = (double*)(base + L.partial);
     double* etrip = (double*)(base + L.etrip);
@@ -120,7 +133,11 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     BQC_HIP(hipMemcpyAsync(d_orb, plan.orbits.data(), plan.orbits.size() * sizeof(int4),
                            hipMemcpyHostToDevice, st));
     Operands ops;
-    if (ntrip > 0) launch_prepare(prec, in, base + L.ops, &ops, st);
+    VirAux aux;
+    if (ntrip > 0) {
+        launch_prepare(prec, in, base + L.ops, &ops, st, form);
+        if (form == FORM_VIR) aux = launch_vir_aux(in, base + L.aux, st);
+    }
     hipEvent_t e_prep = mark(want, st);
 
     // Two H buffers: the contraction of batch b+1 (stream st, MFMA-bound)
@@ -128,14 +145,21 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     const int t_begin = (int)plan.begin, t_end = (int)plan.end;
     auto gemm_of = [&](int b0, int nb, int k) {
         GemmLaunch g;
-        g.o = o; g.v = v; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf[k];
+        g.o = o; g.v = v; g.form = form; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf[k];
         return gemm_call(prec, g);
     };
     auto epi_of = [&](int b0, int nb, int k) {
         EpiLaunch e;
-        e.o = o; e.v = v; e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf[k];
-        e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
-        e.t2 = in.t2; e.fock_ov = in.fock_ov;
+        e.ntrip = nb; e.trip = d_trip + b0; e.hbuf = hbuf[k];
+        if (form == FORM_VIR) {  // triples of virtuals, tiles of occupied indices
+            e.o = v; e.v = o;
+            e.eps_o = aux.neg_eps_v; e.eps_v = aux.neg_eps_o; e.t1 = aux.t1_t; e.ovov = aux.ovov_t;
+            e.t2 = aux.t2_t; e.fock_ov = aux.fock_t;
+        } else {
+            e.o = o; e.v = v;
+            e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
+            e.t2 = in.t2; e.fock_ov = in.fock_ov;
+        }
         e.orbits = d_orb; e.norbit = norbit; e.partial = partial;
         return epilogue_call(prec, e);
     };
@@ -242,12 +266,13 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
-// Device pointer of the per-triple energies and the total inside a workspace.
-double* workspace_etrip(void* ws, int o, int v, int precision) {
-    return (double*)((char*)ws + layout(o, v, precision).etrip);
+// Device pointer of the per-triple energies and the total inside a workspace
+// (neither offset depends on the f_ov block).
+double* workspace_etrip(void* ws, int o, int v, int precision, int form) {
+    return (double*)((char*)ws + layout(o, v, precision, form, false).etrip);
 }
-double* workspace_energy(void* ws, int o, int v, int precision) {
-    return (double*)((char*)ws + layout(o, v, precision).energy);
+double* workspace_energy(void* ws, int o, int v, int precision, int form) {
+    return (double*)((char*)ws + layout(o, v, precision, form, false).energy);
 }
 
 }  // namespace bqc

@@ -33,14 +33,14 @@ hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 
 namespace bqc {
 // the solve writes a value derived from (o, v) into the workspace energy slot
-int64_t workspace_bytes(int o, int v, int) { return (int64_t)(o * 7 + v) * 256 + 4096; }
+int64_t workspace_bytes(int o, int v, int, int, bool) { return (int64_t)(o * 7 + v) * 256 + 4096; }
 int64_t input_bytes(int o, int v) {
     const int64_t n = (int64_t)o + v + (int64_t)o * v + (int64_t)o * o * v * v + (int64_t)o * v * v * v +
                       (int64_t)o * o * o * v + (int64_t)o * v * o * v;
     return n * 8 + 7 * 256;
 }
-double* workspace_energy(void* ws, int, int, int) { return (double*)ws; }
-Plan make_plan(int o, int v, int precision, int64_t, int64_t) { Plan p; p.o = o; p.v = v; p.precision = precision; return p; }
+double* workspace_energy(void* ws, int, int, int, int) { return (double*)ws; }
+Plan make_plan(int o, int v, int precision, int64_t, int64_t, int) { Plan p; p.o = o; p.v = v; p.precision = precision; return p; }
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double*, hipStream_t, hipStream_t, bool,
                    SolveStats* st, bool) {
     // touch the whole workspace and read every input element, like the device would

@@ -39,11 +39,12 @@ def test_footprint_grows_with_size_and_shrinks_with_precision():
     assert f32 > 0
 
 
-def _call(o, v, arrays, E=True, precision=0, triple_range=(0, 0)):
+def _call(o, v, arrays, E=True, precision=0, triple_range=(0, 0), formulation=0):
     ptrs = [None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrays]
     e = ctypes.c_double(123.0)
     opts = binding.TOpts()
     opts.precision = precision
+    opts.formulation = formulation
     opts.triple_begin, opts.triple_end = triple_range
     rc = bqc.lib().bqc_t_energy_ex(o, v, *ptrs, ctypes.byref(opts), ctypes.byref(e) if E else None, None)
     return rc, e.value
@@ -73,6 +74,26 @@ def test_triple_range_checks():
         rc, e = _call(4, 6, arr, triple_range=rng)
         assert rc == binding.EINVAL and e == 123.0, rng
         assert "triple range" in bqc.last_error()
+
+
+def test_formulation_checks():
+    x = make_inputs(4, 6, 12, 0)
+    arr = list(x.arrays())
+    for f in (-1, 2, 7):
+        rc, e = _call(4, 6, arr, formulation=f)
+        assert rc == binding.EINVAL and e == 123.0 and "formulation" in bqc.last_error()
+    # the virtual-triple loop has no FP8 contraction
+    rc, e = _call(4, 6, arr, precision=3, formulation=1)
+    assert rc == binding.EINVAL and e == 123.0
+    # its shares count virtual triples: nvir = 6 has 50 of them, nocc = 4 only 16
+    assert bqc.num_triples(6) == 50
+    for rng in [(0, 51), (50, 51), (3, 3)]:
+        rc, e = _call(4, 6, arr, triple_range=rng, formulation=1)
+        assert rc == binding.EINVAL and e == 123.0 and "triple range" in bqc.last_error(), rng
+    # a share valid only for the virtual count passes the argument checks
+    # (it then fails for want of a device here, or runs on one)
+    rc, _ = _call(4, 6, arr, triple_range=(16, 50), formulation=1)
+    assert rc != binding.EINVAL
 
 
 def test_density_fitting_argument_checks():
