@@ -10,6 +10,10 @@ Prints ONE JSON line.  `value` is (T) TFLOP/s of the fastest contraction
 precision whose energy meets the accuracy gate against FP64 (relative error
 <= 1e-6 at this size; the literal 1 uEh is below the FP64 rounding of an
 energy this large).  F_alg = 12 * n_triples * v^3 * (v + o).
+
+--formulation virtual runs the loop over unique virtual triples instead
+(the paper's loop order, tensors over the occupied indices); its own
+algorithmic count is 12 * n_virtual_triples * o^3 * (v + o).
 """
 from __future__ import annotations
 
@@ -59,6 +63,8 @@ def parse():
     ap.add_argument("--df", action="store_true",
                     help="also time the headline precision through bqc_t_energy_df, with (ia|bc) formed on "
                          "the device from the density-fitting factors")
+    ap.add_argument("--formulation", default="occupied", choices=["occupied", "virtual"],
+                    help="loop over unique occupied triples (default) or unique virtual triples")
     ap.add_argument("--rate-frac", type=float, default=0.7,
                     help="serving open loop: arrival rate as a fraction of the closed-loop req/s (0: skip)")
     return ap.parse_args()
@@ -380,9 +386,14 @@ def main():
         nbytes = x.nbytes()
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t_gen
-    F = flops_alg(o, v)
+    form = args.formulation
     bqc.lib()
-    ntrip = bqc.num_triples(o)
+    if form == "virtual":
+        ntrip = bqc.num_triples(v)
+        F = 12.0 * ntrip * float(o) ** 3 * (v + o)
+    else:
+        ntrip = bqc.num_triples(o)
+        F = flops_alg(o, v)
     cuts = [round(ntrip * q / shares) for q in range(shares + 1)]
     print(f"[bench] workload {args.workload} o={o} v={v} naux={naux} F_alg={F:.3e} "
           f"inputs {nbytes / 1e9:.2f} GB generated {'on the GPU' if on_device else 'on the host'} "
@@ -392,11 +403,12 @@ def main():
         """One solve as `shares` consecutive triple shares; E_T is their
         fixed-order sum and the stats are summed over the shares."""
         if shares == 1:
-            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=timing, stats=True)
+            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=timing, stats=True, formulation=form)
             return e, ex["stats"]
         tot, agg, t0 = 0.0, None, time.perf_counter()
         for q, (b, e_) in enumerate(zip(cuts[:-1], cuts[1:])):
-            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=timing, stats=True, triple_range=(b, e_))
+            e, ex = bqc.t_energy(o, v, *dev, precision=prec, timing=timing, stats=True, triple_range=(b, e_),
+                                 formulation=form)
             tot += e
             st = ex["stats"]
             agg = dict(st) if agg is None else {k: (agg[k] + st[k] if k in ("gemm_s", "epilogue_s", "gemm_launches",
@@ -461,7 +473,7 @@ def main():
     flops_launch = F / max(hr.get("gemm_launches_per_step", 1), 1)
     achieved = flops_launch / hr["gemm_avg_s"] / 1e12
     peak = PEAK_TFLOPS[head]
-    traffic = traffic_from_profiles("h_gemm", args.workload, head)
+    traffic = traffic_from_profiles("h_gemm", args.workload, head) if form == "occupied" else None
     out = {
         "metric": METRIC,
         "value": round(hr["tflops"], 3),
@@ -476,7 +488,7 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp8": "fp8"}[head],
         "data": "synthetic (seeded DF factors, MP1 t2, random t1)" + ("; generated on the GPU" if on_device else ""),
         "config": {"workload": args.workload, "shares_per_solve": shares, "nocc": o, "nvir": v, "naux": naux, "seed": seed,
-                   "precision": head, "parallelism": "single-GPU"},
+                   "precision": head, "formulation": form, "parallelism": "single-GPU"},
         "E_T": hr["E_T"],
         "E_T_fp64": e64,
         "dE_uEh_vs_fp64": hr.get("dE_uEh_vs_fp64"),

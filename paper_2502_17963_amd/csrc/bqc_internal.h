@@ -111,12 +111,11 @@ constexpr int FORM_OCC = 0, FORM_VIR = 1;
 // One launch of the contraction kernel covers a batch of triples.
 struct GemmLaunch {
     int o, v;
-    int form;              // FORM_OCC or FORM_VIR (then the triples are virtual and the
-                           // planes, rows and columns of H run over the occupied indices)
     int ntrip;             // triples in the batch
     const int4* trip;      // (i, j, k, m) per triple in the batch
     Operands ops;
-    void* hbuf;            // [ntrip][3] pairs of hpair_elems(v) blocked elements in the H precision
+    void* hbuf;            // [ntrip][3] pairs of hpair_elems(n) blocked elements in the H precision
+                           // (n = v, or o for FORM_VIR)
 };
 
 // The epilogue is written for triples (i, j, k) of one orbital space and
@@ -125,7 +124,7 @@ struct GemmLaunch {
 // [o][v][o][v], t2 [o][o][v][v] and fock_ov [o][v] in those roles.  The
 // occupied-triple loop passes the inputs as they are; the virtual-triple loop
 // passes o = nvir, v = nocc, -eps_v, -eps_o and the transposed arrays
-// t1[a][i], (ai|bj), t2[a][b][i][j], f[a][i] (every term of V and of Z is
+// t1[a][i], (ia|jb) as [a][b][i][j], t2[a][b][i][j], f[a][i] (every term of V and of Z is
 // symmetric in the two spaces, and the sign flip keeps D = sum over the
 // triple's energies minus the tiles').
 struct EpiLaunch {
@@ -136,7 +135,8 @@ struct EpiLaunch {
     const double* eps_o;
     const double* eps_v;
     const double* t1;
-    const double* ovov;
+    const double* ovov;    // (px|qy) at p * ovov_sp + x * ovov_sx + q * ovov_sq + y
+    int64_t ovov_sp, ovov_sx, ovov_sq;
     const double* t2;      // t2[i][j][a][b] (used with fock_ov)
     const double* fock_ov; // nullptr: canonical reference; else f_ia [o][v]
     const int4* orbits;    // (A, B, C, |stabiliser|) with A >= B >= C
@@ -202,9 +202,10 @@ void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* 
                     hipStream_t st, int form = FORM_OCC);
 
 // Transposed FP64 inputs of the virtual-triple loop's epilogue (see
-// EpiLaunch), built once per solve: -eps_v, -eps_o, t1[a][i], (ai|bj) as
-// ovov_t[a][i][b][j], and with a non-canonical reference t2[a][b][i][j]
-// and f[a][i].
+// EpiLaunch), built once per solve: -eps_v, -eps_o, t1[a][i], (ia|jb) as
+// ovov_t[a][b][i][j] (an o x o matrix per virtual pair, so that the
+// epilogue's 8 x 8 blocks are compact), and with a non-canonical reference
+// t2[a][b][i][j] and f[a][i].
 struct VirAux {
     double *neg_eps_v = nullptr, *neg_eps_o = nullptr, *t1_t = nullptr, *ovov_t = nullptr;
     double *t2_t = nullptr, *fock_t = nullptr;
@@ -217,7 +218,9 @@ int64_t prepare_bytes(int precision, int o, int v);
 int df_block_planes(int o, int v);
 int64_t df_scratch_elems(int o, int v);
 
-KernelCall gemm_call(int precision, const GemmLaunch& g);
+// form = FORM_VIR: the triples of g are virtual and the planes, rows and
+// columns of H run over the occupied indices.
+KernelCall gemm_call(int precision, const GemmLaunch& g, int form = FORM_OCC);
 // Contraction wave tile (16-blocks per side) for rows and columns of size n;
 // tiles of min_wb .. 5 blocks are considered.
 int wave_blocks(int n, int min_wb = 2);

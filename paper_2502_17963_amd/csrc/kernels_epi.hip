@@ -65,7 +65,6 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     const HT* Hc = Hb + hp;
     // first element of block (X, Y, Z) of a blocked H buffer
     auto blk = [&](const HT* H, int X, int Y, int Z) { return H + (((int64_t)X * nt + Y) * nt + Z) * E_T3; };
-    const int64_t ov = (int64_t)e.o * v;
 
     constexpr int T = EPI_T, T2 = EPI_T * EPI_T;
     __shared__ double Ws[6][E_T3];
@@ -102,7 +101,7 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
         // m = 0: (jb|kc) with b in X, c in Y; 1: (ia|kc); 2: (ia|jb)
         const int p = m == 0 ? j : i, q = m == 2 ? j : k;
         // unconditional load at a clamped (valid) index, then masked: no branch
-        const double g = e.ovov[((int64_t)p * v + min(x, v - 1)) * ov + (int64_t)q * v + min(y, v - 1)];
+        const double g = e.ovov[p * e.ovov_sp + min(x, v - 1) * e.ovov_sx + q * e.ovov_sq + min(y, v - 1)];
         gv[n] = keep_if(g, el < 27 * T2 && x < v && y < v);
     }
     // f_ov term loads (same shapes as the singles term)

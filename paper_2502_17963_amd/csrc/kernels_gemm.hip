@@ -196,6 +196,100 @@ __device__ __forceinline__ void roles(int h, int i, int j, int k, int& q, int& P
     else { q = k; P = i; R = j; }
 }
 
+// The MFMA products of one staged chunk for one wave: WB x WB 16 x 16
+// blocks, A fragments from LDS rows arow0 + 16 m + (lane % 16), B fragments
+// from rows brow0 + 16 n + (lane % 16) of the stage at L0 (FP8: exponent
+// words of the staged rows at Ls).
+template <int PREC, int WB>
+__device__ __forceinline__ void stage_products(typename Mode<PREC>::Acc (&acc)[WB][WB], const char* L0,
+                                               const uint32_t* Ls, int arow0, int brow0, int fr, int fg) {
+    typedef typename Mode<PREC>::E E;
+    if constexpr (PREC == 3) {
+        // The FP8 16x16x128 MFMA reads lane group g's 32 bytes as
+        // contraction elements [16g, 16g+16) and [64+16g, 64+16g+16) and
+        // takes from lane group g the exponent of elements [32g, 32g+32).
+        // Feeding units g and 4+g of the staged row places every staged
+        // 32-element block b (units 2b, 2b+1) exactly in the MFMA's block
+        // b, whose exponent, byte b of the row's scale word, group b holds.
+        i8v af[WB], bfr[WB];
+        int sa[WB], sb[WB];
+#pragma unroll
+        for (int m = 0; m < WB; ++m) {
+            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+            const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
+            const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
+            const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
+            const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
+            af[m] = i8v{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+            bfr[m] = i8v{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+            sa[m] = (int)((Ls[ra] >> (8 * fg)) & 0xffu);
+            sb[m] = (int)((Ls[rb] >> (8 * fg)) & 0xffu);
+        }
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[m], bfr[nn], acc[m][nn], 0, 0,
+                                                                              0, sa[m], 0, sb[nn]);
+    } else if constexpr (PREC == 2) {
+        bf8 ah[WB], al[WB], bh[WB], bl[WB];
+#pragma unroll
+        for (int m = 0; m < WB; ++m) {
+            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+            ah[m] = *(const bf8*)(L0 + lds_off(ra, fg));
+            al[m] = *(const bf8*)(L0 + lds_off(ra, 4 + fg));
+            bh[m] = *(const bf8*)(L0 + lds_off(rb, fg));
+            bl[m] = *(const bf8*)(L0 + lds_off(rb, 4 + fg));
+        }
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh[nn], acc[m][nn], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bl[nn], acc[m][nn], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh[nn], acc[m][nn], 0, 0, 0);
+    } else {
+        constexpr int NS = (PREC == 0) ? 4 : 8;  // MFMA K-steps per stage
+        E af[WB][NS], bfr[WB][NS];
+#pragma unroll
+        for (int m = 0; m < WB; ++m) {
+            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+            const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
+            const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
+            const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
+            const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
+            const E* pa0 = (const E*)&a0; const E* pa1 = (const E*)&a1;
+            const E* pb0 = (const E*)&b0; const E* pb1 = (const E*)&b1;
+#pragma unroll
+            for (int s = 0; s < NS / 2; ++s) {
+                af[m][s] = pa0[s]; af[m][NS / 2 + s] = pa1[s];
+                bfr[m][s] = pb0[s]; bfr[m][NS / 2 + s] = pb1[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int m = 0; m < WB; ++m)
+#pragma unroll
+                for (int nn = 0; nn < WB; ++nn) {
+                    if constexpr (PREC == 0)
+                        acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m][s], bfr[nn][s],
+                                                                           acc[m][nn], 0, 0, 0);
+                    else
+                        acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m][s], bfr[nn][s],
+                                                                           acc[m][nn], 0, 0, 0);
+                }
+    }
+}
+
 template <int PREC, class G, int FORM>
 __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile_u,
                                                               int ntile_w, int per_xcd) {
@@ -332,91 +426,7 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
 
     const int fr = lane & 15, fg = lane >> 4;
     auto compute = [&](int buf) {
-        const char* L0 = lds[buf];
-        if constexpr (PREC == 3) {
-            // The FP8 16x16x128 MFMA reads lane group g's 32 bytes as
-            // contraction elements [16g, 16g+16) and [64+16g, 64+16g+16) and
-            // takes from lane group g the exponent of elements [32g, 32g+32).
-            // Feeding units g and 4+g of the staged row places every staged
-            // 32-element block b (units 2b, 2b+1) exactly in the MFMA's block
-            // b, whose exponent, byte b of the row's scale word, group b holds.
-            i8v af[WB], bfr[WB];
-            int sa[WB], sb[WB];
-#pragma unroll
-            for (int m = 0; m < WB; ++m) {
-                const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-                const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
-                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
-                const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
-                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
-                af[m] = i8v{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
-                bfr[m] = i8v{(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
-                sa[m] = (int)((lds_s[buf][ra] >> (8 * fg)) & 0xffu);
-                sb[m] = (int)((lds_s[buf][rb] >> (8 * fg)) & 0xffu);
-            }
-#pragma unroll
-            for (int m = 0; m < WB; ++m)
-#pragma unroll
-                for (int nn = 0; nn < WB; ++nn)
-                    acc[m][nn] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[m], bfr[nn], acc[m][nn], 0, 0,
-                                                                                  0, sa[m], 0, sb[nn]);
-        } else if constexpr (PREC == 2) {
-            bf8 ah[WB], al[WB], bh[WB], bl[WB];
-#pragma unroll
-            for (int m = 0; m < WB; ++m) {
-                const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-                ah[m] = *(const bf8*)(L0 + lds_off(ra, fg));
-                al[m] = *(const bf8*)(L0 + lds_off(ra, 4 + fg));
-                bh[m] = *(const bf8*)(L0 + lds_off(rb, fg));
-                bl[m] = *(const bf8*)(L0 + lds_off(rb, 4 + fg));
-            }
-#pragma unroll
-            for (int m = 0; m < WB; ++m)
-#pragma unroll
-                for (int nn = 0; nn < WB; ++nn)
-                    acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh[nn], acc[m][nn], 0, 0, 0);
-#pragma unroll
-            for (int m = 0; m < WB; ++m)
-#pragma unroll
-                for (int nn = 0; nn < WB; ++nn)
-                    acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bl[nn], acc[m][nn], 0, 0, 0);
-#pragma unroll
-            for (int m = 0; m < WB; ++m)
-#pragma unroll
-                for (int nn = 0; nn < WB; ++nn)
-                    acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh[nn], acc[m][nn], 0, 0, 0);
-        } else {
-            constexpr int NS = (PREC == 0) ? 4 : 8;  // MFMA K-steps per stage
-            E af[WB][NS], bfr[WB][NS];
-#pragma unroll
-            for (int m = 0; m < WB; ++m) {
-                const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-                const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
-                const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
-                const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
-                const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
-                const E* pa0 = (const E*)&a0; const E* pa1 = (const E*)&a1;
-                const E* pb0 = (const E*)&b0; const E* pb1 = (const E*)&b1;
-#pragma unroll
-                for (int s = 0; s < NS / 2; ++s) {
-                    af[m][s] = pa0[s]; af[m][NS / 2 + s] = pa1[s];
-                    bfr[m][s] = pb0[s]; bfr[m][NS / 2 + s] = pb1[s];
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-                for (int m = 0; m < WB; ++m)
-#pragma unroll
-                    for (int nn = 0; nn < WB; ++nn) {
-                        if constexpr (PREC == 0)
-                            acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m][s], bfr[nn][s],
-                                                                               acc[m][nn], 0, 0, 0);
-                        else
-                            acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m][s], bfr[nn][s],
-                                                                               acc[m][nn], 0, 0, 0);
-                    }
-        }
+        stage_products<PREC, WB>(acc, lds[buf], lds_s[buf], arow0, brow0, fr, fg);
     };
 
     load(0);
@@ -449,6 +459,145 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
             }
 }
 
+// The loop over virtual triples has small planes (n = nocc rows and
+// columns), and in every segment one of the two factors does not depend on
+// the plane y: the Row factor in segments 0 and 3 ((uA|Bd), t_lu^BA) and the
+// Col factor in segments 1 and 2 (t_lw^BC, (wC|Bd)).  A work group of PL_NP
+// waves therefore takes PL_NP consecutive planes of one pair of one triple,
+// one plane per wave (all n x n of it, WB x WB 16-blocks), and stages the
+// plane-independent factor once per chunk for all of them: LDS rows
+// [0, 16 WB) hold it, rows [16 WB (1 + p), 16 WB (2 + p)) the factor of
+// plane y0 + p.  Same chunk-major operands, staging, swizzle and MFMA
+// products as h_gemm_kernel.
+constexpr int PL_NP = 4;
+
+template <int PREC, int WB>
+__global__ __launch_bounds__(64 * PL_NP, 1) void h_gemm_planes_kernel(GemmLaunch g, int n_wg, int ngrp,
+                                                                      int per_xcd) {
+    constexpr int NTHR = 64 * PL_NP, NPAD = 16 * WB, NROW = (1 + PL_NP) * NPAD;
+    constexpr int NVEC = (NROW * 8 + NTHR - 1) / NTHR;
+    typedef Mode<PREC> M;
+    typedef typename M::Acc Acc;
+    typedef typename M::HT HT;
+    constexpr int KC = M::KC;
+
+    const int hw = blockIdx.x;
+    const int L = (hw % 8) * per_xcd + hw / 8;  // XCD-aware order, as in h_gemm_kernel
+    if (L >= n_wg) return;
+    const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
+    const int n = o;  // planes, rows and columns run over the occupied indices
+    int rem = L;
+    const int grp = rem % ngrp; rem /= ngrp;
+    const int h = rem % 3;
+    const int t = rem / 3;
+    const int4 tr = g.trip[t];
+    int B, A, C;  // middle virtual of the pair and the other two
+    roles(h, tr.x, tr.y, tr.z, B, A, C);
+    const int y0 = grp * PL_NP;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ __attribute__((aligned(16))) char lds[2][NROW * ROWB];
+
+    Acc acc[WB][WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+    // staged row of this thread's vector e: (tid / 8) + e NTHR / 8; block 0
+    // is the plane-independent factor, block 1 + p the factor of plane y0 + p
+    const int qv = tid & 7;
+    int off[NVEC], plane[NVEC];
+    bool ok[NVEC];
+#pragma unroll
+    for (int e = 0; e < NVEC; ++e) {
+        const int row = (tid >> 3) + e * (NTHR / 8);
+        const int blkrow = row / NPAD, r = row % NPAD;
+        plane[e] = blkrow - 1;  // -1: plane-independent factor
+        ok[e] = row < NROW && r < n && (blkrow == 0 || y0 + blkrow - 1 < n);
+        off[e] = r * ROWB + qv * 16;
+    }
+
+    const int nch_v = Kv / KC, nch_o = Ko / KC;
+    const int nch = 2 * nch_v + 2 * nch_o;
+    auto chunk_seg = [&](int c, int& s, int& kb) {
+        if (c < nch_v) { s = 0; kb = c; }
+        else if (c < nch_v + nch_o) { s = 1; kb = c - nch_v; }
+        else if (c < 2 * nch_v + nch_o) { s = 2; kb = c - nch_v - nch_o; }
+        else { s = 3; kb = c - 2 * nch_v - nch_o; }
+    };
+    const int64_t blk = (int64_t)n * ROWB;  // bytes of one chunk block (all n rows)
+
+    u4 reg[NVEC];
+    auto load = [&](int c) {
+        int s, kb;
+        chunk_seg(c, s, kb);
+        // plane-independent matrix and the plane-y matrix y * v + X of this segment
+        // (the matrices of seg_geom_vir)
+        int arr_s, arr_y, X;
+        int64_t mat_s;
+        switch (s) {
+            case 0: arr_s = 0; mat_s = (int64_t)A * v + B; arr_y = 1; X = C; break;  // (uA|Bd) | t_wy^Cd
+            case 1: arr_s = 2; mat_s = (int64_t)B * v + C; arr_y = 3; X = A; break;  // t_lw^BC | -(uA|yl)
+            case 2: arr_s = 0; mat_s = (int64_t)C * v + B; arr_y = 1; X = A; break;  // (wC|Bd) | t_uy^Ad
+            default: arr_s = 2; mat_s = (int64_t)B * v + A; arr_y = 3; X = C; break;  // t_lu^BA | -(wC|yl)
+        }
+        const int nchunk = (s == 0 || s == 2) ? nch_v : nch_o;
+        const char* sb = arr_base(g.ops, arr_s) + (mat_s * nchunk + kb) * blk;
+        const char* yb = arr_base(g.ops, arr_y) + ((int64_t)X * nchunk + kb) * blk;
+        const int64_t ystep = (int64_t)v * nchunk * blk;  // next plane: matrix + v
+#pragma unroll
+        for (int e = 0; e < NVEC; ++e) {
+            const char* base = plane[e] < 0 ? sb : yb + (int64_t)(y0 + plane[e]) * ystep;
+            reg[e] = ok[e] ? *(const u4*)(base + off[e]) : u4{0, 0, 0, 0};
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < NVEC; ++e) {
+            const int row = (tid >> 3) + e * (NTHR / 8);
+            if ((NVEC * NTHR == NROW * 8) || row < NROW) *(u4*)(&lds[buf][lds_off(row, qv)]) = reg[e];
+        }
+    };
+
+    const int fr = lane & 15, fg = lane >> 4;
+    const int own = NPAD * (1 + wave);  // first LDS row of this wave's plane factor
+    auto compute = [&](int buf, int c) {
+        int s, kb;
+        chunk_seg(c, s, kb);
+        const bool shared_row = (s == 0 || s == 3);  // the Row factor is the shared one
+        stage_products<PREC, WB>(acc, lds[buf], nullptr, shared_row ? 0 : own, shared_row ? own : 0, fr, fg);
+    };
+
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        if (c + 1 < nch) load(c + 1);
+        compute(c & 1, c);
+        if (c + 1 < nch) store((c + 1) & 1);
+        __syncthreads();
+    }
+
+    const int y = y0 + wave;
+    if (y >= n) return;
+    const int nt = ceil_div(n, EPI_T);
+    HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(n) + (int64_t)(y >> 3) * nt * nt * 512 +
+              (y & 7) * 64;
+#pragma unroll
+    for (int m = 0; m < WB; ++m)
+#pragma unroll
+        for (int nn = 0; nn < WB; ++nn) {
+            const int w = nn * 16 + fr;
+            const int wo = (w >> 3) * 512 + (w & 7);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int u = m * 16 + M::row(lane, r);
+                if (u < n && w < n) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
+            }
+        }
+}
+
 }  // namespace
 
 namespace {
@@ -478,13 +627,36 @@ double block_use(int nblk, int wb) {
     return (double)nblk * nblk / slots;
 }
 
+template <int PREC, int WB>
+KernelCall planes_call(const GemmLaunch& g) {
+    const int ngrp = ceil_div(g.o, PL_NP);
+    const int64_t n64 = (int64_t)g.ntrip * 3 * ngrp;
+    if (n64 > ((int64_t)1 << 31) - 8) throw Error(-1, "contraction grid too large");
+    const int n_wg = (int)n64;
+    const int per_xcd = ceil_div(n_wg, 8);
+    KernelCall k;
+    k.fn = (const void*)&h_gemm_planes_kernel<PREC, WB>;
+    k.grid = dim3(per_xcd * 8);
+    k.block = dim3(64 * PL_NP);
+    k.arg(g).arg(n_wg).arg(ngrp).arg(per_xcd);
+    return k;
+}
+
 template <int PREC>
-KernelCall mode_call(const GemmLaunch& g) {
-    if (g.form == FORM_VIR) {
+KernelCall mode_call(const GemmLaunch& g, int form) {
+    if (form == FORM_VIR) {
         // occupied spaces are small: tiles down to one 16 x 16 block per wave
         if constexpr (PREC == 3) {
             throw Error(-1, "the virtual-triple loop has no FP8 contraction");
         } else {
+            // up to 64 occupied orbitals: one plane per wave (h_gemm_planes_kernel)
+            switch (ceil_div(g.o, 16)) {
+                case 1: return planes_call<PREC, 1>(g);
+                case 2: return planes_call<PREC, 2>(g);
+                case 3: return planes_call<PREC, 3>(g);
+                case 4: return planes_call<PREC, 4>(g);
+                default: break;
+            }
             switch (wave_blocks(g.o, 1)) {
                 case 1: return geo_call<PREC, Geo<2, 2, 1>, FORM_VIR>(g);
                 case 2: return geo_call<PREC, Geo<2, 2, 2>, FORM_VIR>(g);
@@ -523,12 +695,12 @@ int wave_blocks(int n, int min_wb) {
 // A 320 x 160 tile with 8 waves loads a quarter fewer operand bytes per flop
 // than 160 x 160 but measured slower (FP32 7.9 s vs 7.6 s, BF16x3 3.7 s vs
 // 3.4 s per solve at o = 32, v = 300).
-KernelCall gemm_call(int precision, const GemmLaunch& g) {
+KernelCall gemm_call(int precision, const GemmLaunch& g, int form) {
     switch (precision) {
-        case 0: return mode_call<0>(g);
-        case 1: return mode_call<1>(g);
-        case 2: return mode_call<2>(g);
-        case 3: return mode_call<3>(g);
+        case 0: return mode_call<0>(g, form);
+        case 1: return mode_call<1>(g, form);
+        case 2: return mode_call<2>(g, form);
+        case 3: return mode_call<3>(g, form);
         default: throw Error(-1, "unsupported precision for the MFMA contraction");
     }
 }

@@ -446,7 +446,7 @@ namespace {
 
 // dst[e] for e < n: the transposes of the epilogue's inputs (one thread per
 // destination element).  kind 0: dst[a][i] = src[i][a] (t1, f_ov; o x v
-// source); 1: dst[a][i][b][j] = src[i][a][j][b] ((ia|jb)); 2: dst[a][b][i][j]
+// source); 1: dst[a][b][i][j] = src[i][a][j][b] ((ia|jb)); 2: dst[a][b][i][j]
 // = src[i][j][a][b] (t2); 3: dst[x] = -src[x].
 __global__ void vir_aux_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int kind,
                                int o, int v) {
@@ -455,20 +455,13 @@ __global__ void vir_aux_kernel(const double* __restrict__ src, double* __restric
         if (kind == 0) {
             const int64_t a = e / o, i = e % o;
             si = i * v + a;
-        } else if (kind == 1) {
-            int64_t r = e;
-            const int64_t j = r % o; r /= o;
-            const int64_t b = r % v; r /= v;
-            const int64_t i = r % o;
-            const int64_t a = r / o;
-            si = ((i * v + a) * o + j) * v + b;
-        } else if (kind == 2) {
+        } else if (kind == 1 || kind == 2) {  // destination [a][b][i][j]
             int64_t r = e;
             const int64_t j = r % o; r /= o;
             const int64_t i = r % o; r /= o;
             const int64_t b = r % v;
             const int64_t a = r / v;
-            si = ((i * o + j) * v + a) * v + b;
+            si = kind == 1 ? ((i * v + a) * o + j) * v + b : ((i * o + j) * v + a) * v + b;
         } else {
             dst[e] = -src[e];
             continue;

@@ -145,8 +145,8 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
     const int t_begin = (int)plan.begin, t_end = (int)plan.end;
     auto gemm_of = [&](int b0, int nb, int k) {
         GemmLaunch g;
-        g.o = o; g.v = v; g.form = form; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf[k];
-        return gemm_call(prec, g);
+        g.o = o; g.v = v; g.ntrip = nb; g.trip = d_trip + b0; g.ops = ops; g.hbuf = hbuf[k];
+        return gemm_call(prec, g, form);
     };
     auto epi_of = [&](int b0, int nb, int k) {
         EpiLaunch e;
@@ -154,10 +154,12 @@ void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_en
         if (form == FORM_VIR) {  // triples of virtuals, tiles of occupied indices
             e.o = v; e.v = o;
             e.eps_o = aux.neg_eps_v; e.eps_v = aux.neg_eps_o; e.t1 = aux.t1_t; e.ovov = aux.ovov_t;
+            e.ovov_sp = (int64_t)v * o * o; e.ovov_sx = o; e.ovov_sq = (int64_t)o * o;
             e.t2 = aux.t2_t; e.fock_ov = aux.fock_t;
         } else {
             e.o = o; e.v = v;
             e.eps_o = in.eps_o; e.eps_v = in.eps_v; e.t1 = in.t1; e.ovov = in.ovov;
+            e.ovov_sp = (int64_t)v * o * v; e.ovov_sx = (int64_t)o * v; e.ovov_sq = v;
             e.t2 = in.t2; e.fock_ov = in.fock_ov;
         }
         e.orbits = d_orb; e.norbit = norbit; e.partial = partial;

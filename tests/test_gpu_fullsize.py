@@ -76,3 +76,32 @@ def test_df_bf16x3_matches_ovvv_input(large):
     print(f"df bf16x3 E={e_df:.12e} ovvv-input E={e_in:.12e} fp64 {e64:.12e}", flush=True)
     assert abs(e_df - e_in) <= 1e-7 * abs(e_in)
     assert abs(e_df - e64) <= 1e-6 * abs(e64)
+
+
+def test_virtual_formulation_sampled_triples_and_total(large):
+    """The loop over virtual triples at the benchmarked size: its per-virtual-
+    triple energies on a seeded sample against the oracle's (loop over
+    virtual triples, one at a time), its FP64 total against the occupied
+    loop's, and its split-BF16x3 total against FP64 at the mixed gate."""
+    import torch
+
+    from oracle.virtual_loop import virtual_triple_energy, virtual_triple_table
+    bqc, x, dev, e64, _ = large
+    o, v = x.nocc, x.nvir
+    e_v, ex = bqc.t_energy(o, v, *dev, precision="fp64", triple_energies=True, formulation="virtual")
+    torch.cuda.synchronize()
+    trip = ex["triples"]
+    table = virtual_triple_table(v)
+    assert len(trip) == len(table)
+    rng = np.random.default_rng(7)
+    picks = sorted(set([0, 1, len(table) - 1] + list(rng.choice(len(table), 4, replace=False))))
+    for n in picks:
+        a, b, c, m = table[n]
+        ref = virtual_triple_energy(a, b, c, m, *x.arrays())
+        print(f"virtual triple {n} ({a},{b},{c}) gpu={trip[n]:.15e} oracle={ref:.15e}", flush=True)
+        assert abs(trip[n] - ref) <= 1e-10 * max(abs(ref), 1e-300)
+    print(f"virtual fp64 E={e_v:.12e} occupied fp64 E={e64:.12e}", flush=True)
+    assert abs(e_v - e64) <= 1e-12 * abs(e64)
+    e_b = bqc.t_energy(o, v, *dev, precision="bf16x3", formulation="virtual")
+    torch.cuda.synchronize()
+    assert abs(e_b - e64) <= 1e-6 * abs(e64)
