@@ -155,3 +155,16 @@ def test_triple_shares_add_up_to_the_solve():
         parts.append(es)
     torch.cuda.synchronize()
     assert abs(sum(parts) - e_all) <= 1e-13 * abs(e_all)
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(70, 5, 30, 1), (66, 4, 30, 2)])
+def test_many_occupied_fp64(o, v, naux, seed):
+    """More than 64 occupied orbitals: the contraction runs on the general
+    tile kernel instead of one plane per wave."""
+    bqc = _bqc()
+    print(f"case virtual many-occupied o={o} v={v} seed={seed}", flush=True)
+    x = make_inputs(o, v, naux, seed)
+    ref = vl.t_energy_virtual_loop(*x.arrays())
+    for prec, tol in (("fp64", FP64_REL), ("bf16x3", 1e-6)):
+        e = bqc.t_energy(o, v, *x.arrays(), precision=prec, formulation="virtual")
+        assert abs(e - ref) <= tol * abs(ref), (prec, e, ref)
