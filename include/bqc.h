@@ -165,7 +165,11 @@ int bqc_t_energy_df(int32_t nocc, int32_t nvir, int32_t naux,
  *   E_MP2 = sum_{ijab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b).
  * Inputs: eps_o[nocc], eps_v[nvir], b_ov[naux][nocc][nvir] (FP64, row-major),
  * borrowed.  Of the options only precision (must be BQC_PREC_FP64), device,
- * inputs_on_device, stream and timing are used (opts may be NULL).  The
+ * inputs_on_device, stream, timing and triple_energies are used (opts may be
+ * NULL); here triple_energies is NULL or a HOST array of nocc(nocc+1)/2
+ * doubles that receives the pair energies e_ij, i <= j in lexicographic
+ * order (e_ij = sum_ab (ia|jb)[2(ia|jb) - (ib|ja)]/D_ij^ab, doubled for
+ * i < j to count the pair (j, i)), of which E_MP2 is the sum.  The
  * integrals are contracted on FP64 MFMA per occupied pair and virtual tile
  * pair with the denominator applied in registers (no four-index tensor is
  * stored); the sum is fixed-order and compensated.  Errors: BQC_EINVAL for

@@ -259,9 +259,12 @@ def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, 
     return _finish(rc, e, st, etrip, ntrip, triple_energies, stats, timing)
 
 
-def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, stats=False):
+def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, stats=False,
+                  pair_energies=False):
     """E_MP2 through bqc_mp2_energy_df (b_ov[naux][nocc][nvir]; FP64).
-    Returns E_MP2, or (E_MP2, stats dict) with stats=True."""
+    Returns E_MP2, or (E_MP2, stats dict) with stats=True; with
+    pair_energies=True, (E_MP2, extras) where extras["pairs"] holds e_ij for
+    i <= j in lexicographic order and extras["stats"] the stats."""
     ptrs, on_dev, keep = _ptrs((eps_o, eps_v, b_ov))
     opts = TOpts()
     opts.device = device
@@ -270,11 +273,17 @@ def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, s
         opts.stream = ctypes.c_void_p(stream)
     elif on_dev:
         opts.stream = ctypes.c_void_p(_torch_stream(eps_o))
+    pairs = None
+    if pair_energies:
+        pairs = np.zeros(max(nocc * (nocc + 1) // 2, 1))
+        opts.triple_energies = pairs.ctypes.data_as(_dp)
     e = ctypes.c_double(0.0)
     st = TStats()
     rc = lib().bqc_mp2_energy_df(nocc, nvir, naux, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
     del keep
     _check(rc)
+    if pair_energies:
+        return e.value, {"pairs": pairs[:nocc * (nocc + 1) // 2], "stats": st.as_dict()}
     return (e.value, st.as_dict()) if stats else e.value
 
 

@@ -294,13 +294,21 @@ int mp2_impl(int32_t o, int32_t v, int32_t naux, const double* eps_o, const doub
         BQC_HIP(hipEventRecord(e0, st));
     }
     struct Ev { hipEvent_t a, b; ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); } } evg{e0, e1};
-    double* d_e = enqueue_mp2(o, v, naux, d_eo, d_ev, d_b, ctx->ws, st, nullptr);
+    double* d_pair = nullptr;
+    double* d_e = enqueue_mp2(o, v, naux, d_eo, d_ev, d_b, ctx->ws, st, &d_pair);
     if (stats) BQC_HIP(hipEventRecord(e1, st));
     BQC_HIP(hipMemcpyAsync(ctx->host_energy, d_e, sizeof(double), hipMemcpyDeviceToHost, st));
+    const int64_t npair = (int64_t)o * (o + 1) / 2;
+    std::vector<double> pairs;
+    if (op.triple_energies) {
+        pairs.resize(npair);
+        BQC_HIP(hipMemcpyAsync(pairs.data(), d_pair, npair * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     BQC_HIP(hipStreamSynchronize(st));
     const double e = *ctx->host_energy;
     if (!std::isfinite(e)) return fail(BQC_EDEVICE, "non-finite energy (device arithmetic failed)");
     *E = e;
+    if (op.triple_energies) std::memcpy(op.triple_energies, pairs.data(), npair * sizeof(double));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         float ms = 0;

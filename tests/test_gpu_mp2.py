@@ -74,3 +74,18 @@ def test_mp2_device_inputs_right_after_torch_work():
     e = bqc.mp2_energy_df(o, v, naux, eo, ev, b)
     ref = mp2_energy(eo.cpu().numpy(), ev.cpu().numpy(), b.cpu().numpy())
     assert abs(e - ref) <= 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("shape", [(6, 30, 120, 0), (9, 130, 301, 4)])
+def test_mp2_pair_energies_match_oracle(shape):
+    from oracle.mp2 import pair_energies
+    bqc = _bqc()
+    o, v, naux, seed = shape
+    print(f"case mp2 pairs o={o} v={v} naux={naux} seed={seed}", flush=True)
+    eo, ev, b = _factors(o, v, naux, seed)
+    ref = np.array([e for _, e in pair_energies(eo, ev, b)])
+    e, ex = bqc.mp2_energy_df(o, v, naux, eo, ev, b, pair_energies=True)
+    got = ex["pairs"]
+    assert got.shape == (o * (o + 1) // 2,)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert abs(e - float(np.sum(got))) <= 1e-13 * abs(e)
