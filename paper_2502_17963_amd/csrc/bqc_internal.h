@@ -28,15 +28,17 @@ struct Error : std::runtime_error {
     } while (0)
 
 // ------------------------------------------------------------------ shapes
-// Virtual-orbital tile of the epilogue: energies are reduced over orbits of
-// EPI_T^3 tiles under the six permutations of (a, b, c).
+// Tile of the epilogue (of virtuals, or of occupied orbitals in the loop
+// over virtual triples): energies are reduced over orbits of EPI_T^3 tiles
+// under the six permutations of the three tile-space indices.
 constexpr int EPI_T = 8;
 
 // The H buffers are stored in EPI_T^3 blocks, so that the epilogue reads every
-// block it needs as one contiguous run: with nt = ceil(v / EPI_T), element
-// (y, u, w) of one pair lies at
+// block it needs as one contiguous run: with n the size of the tile space
+// (nvir, or nocc in the loop over virtual triples) and nt = ceil(n / EPI_T),
+// element (y, u, w) of one pair lies at
 //   ((y / 8 * nt + u / 8) * nt + w / 8) * 512 + (y % 8 * 8 + u % 8) * 8 + w % 8.
-// Elements with an index >= v are never written and never read.
+// Elements with an index >= n are never written and never read.
 __host__ __device__ inline int64_t hpair_elems(int v) {
     const int64_t nt = (v + EPI_T - 1) / EPI_T;
     return nt * nt * nt * EPI_T * EPI_T * EPI_T;
@@ -83,6 +85,8 @@ struct DevInputs {
 //   t2    M = P*o + q, r = u, k = d:  t_Pq^ud
 //   t2l   M = P*v + y, r = u, k = l:  t_lP^yu
 //   hoo   M = q*o + P, r = u, k = l:  -(Pu|ql)
+// In the loop over virtual triples the matrices have o rows instead (same
+// byte counts; the matrix maps are in kernels_prep.hip).
 // FP8: KC = 128 e4m3 bytes per chunk and contraction lengths padded to 128;
 // each row of each chunk also has a 4-byte word of E8M0 exponents, one per
 // 32 elements (scale 2^(byte - 127)), at ((M * nchunk + c) * v + r) * 4.

@@ -23,6 +23,10 @@
 // No floating-point atomics: each work group writes one FP64 partial; the
 // partials are summed per triple and then over triples in a fixed order with
 // Neumaier compensation.
+//
+// The loop over virtual triples runs this same kernel with the two orbital
+// spaces exchanged (triples (a, b, c), tiles of occupied orbitals; the
+// arguments are described with EpiLaunch).
 #include "bqc_internal.h"
 
 namespace bqc {
