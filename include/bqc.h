@@ -104,7 +104,8 @@ typedef struct {
                                  triple (a <= b <= c, lexicographic, a = b = c skipped;
                                  bqc_t_num_triples(nvir) of them), stats->flops is 12 n_triples nocc^3
                                  (nocc + nvir), and BQC_PREC_FP8 is rejected with BQC_EINVAL.  Any
-                                 other value: BQC_EINVAL. */
+                                 other value: BQC_EINVAL.  A solve whose loop has more than 2^31 - 1
+                                 unique triples (nvir > 2343 here) is rejected with BQC_EINVAL. */
 } bqc_t_opts;
 
 #define BQC_FORM_OCCUPIED 0

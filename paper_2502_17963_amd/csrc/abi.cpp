@@ -121,6 +121,8 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
         for (int64_t a = 0; a < (int64_t)o * v; ++a)
             if (!std::isfinite(op.fock_ov[a])) return fail(BQC_EINVAL, "non-finite fock_ov element");
     const int64_t ntrip_all = num_triples(form == FORM_VIR ? v : o);
+    if (ntrip_all > (int64_t)INT32_MAX)
+        return fail(BQC_EINVAL, "more unique triples than one solve supports (2^31 - 1)");
     if (op.triple_end == 0 ? op.triple_begin != 0
                            : (op.triple_begin < 0 || op.triple_begin >= op.triple_end || op.triple_end > ntrip_all))
         return fail(BQC_EINVAL, "triple range outside [0, number of unique triples] or empty");

@@ -96,6 +96,18 @@ def test_formulation_checks():
     assert rc != binding.EINVAL
 
 
+def test_too_many_triples_rejected():
+    # nvir = 2344 has 2.149e9 unique virtual triples, beyond what one solve indexes;
+    # the check precedes any read of the large arrays
+    o, v = 1, 2344
+    assert bqc.num_triples(v) > 2**31 - 1 and bqc.num_triples(2343) <= 2**31 - 1
+    eps_o, eps_v = np.array([-1.0]), np.linspace(0.1, 3.0, v)
+    tiny = np.zeros(4)
+    arr = [eps_o, eps_v, tiny, tiny, tiny, tiny, tiny]
+    rc, e = _call(o, v, arr, formulation=1)
+    assert rc == binding.EINVAL and e == 123.0 and "unique triples" in bqc.last_error()
+
+
 def test_density_fitting_argument_checks():
     from synth import make_df_inputs
     a = [np.ascontiguousarray(x) for x in make_df_inputs(3, 5, 10, 0)]
