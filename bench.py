@@ -63,11 +63,42 @@ def parse():
     ap.add_argument("--df", action="store_true",
                     help="also time the headline precision through bqc_t_energy_df, with (ia|bc) formed on "
                          "the device from the density-fitting factors")
+    ap.add_argument("--fock", action="store_true",
+                    help="also time the headline precision with an f_ov block (non-canonical reference, "
+                         "f_ia ~ N(0, 0.02^2), seeded), against its FP64 solve")
     ap.add_argument("--formulation", default="occupied", choices=["occupied", "virtual"],
                     help="loop over unique occupied triples (default) or unique virtual triples")
     ap.add_argument("--rate-frac", type=float, default=0.7,
                     help="serving open loop: arrival rate as a fraction of the closed-loop req/s (0: skip)")
     return ap.parse_args()
+
+
+def run_fock(args, bqc, dev, o, v, prec, F, seed, form):
+    """The headline precision with an f_ov block (the f_ia t_jk^bc terms of
+    the disconnected triples): time per solve and the energy against the
+    FP64 solve with the same block."""
+    import numpy as np
+    import torch
+    f = torch.from_numpy(np.random.default_rng(1000 + seed).normal(0.0, 0.02, (o, v))).to("cuda:0")
+    torch.cuda.synchronize()
+    e64 = bqc.t_energy(o, v, *dev, precision="fp64", fock_ov=f, formulation=form)
+    for _ in range(args.warmup):
+        bqc.t_energy(o, v, *dev, precision=prec, fock_ov=f, formulation=form)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e, ex = bqc.t_energy(o, v, *dev, precision=prec, fock_ov=f, timing=True, formulation=form)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    st = ex["stats"]
+    rel = abs(e - e64) / abs(e64)
+    rec = {"precision": prec, "E_T": e, "E_T_fp64": e64, "rel_vs_fp64": rel, "s": round(dt, 4),
+           "tflops": round(F / dt / 1e12, 3), "epilogue_avg_s": st["epilogue_s"] / max(st["epilogue_launches"], 1),
+           "gemm_avg_s": st["gemm_s"] / max(st["gemm_launches"], 1)}
+    print(f"[bench] f_ov block {prec}: E_T={e:.12e} rel vs FP64 {rel:.2e} {dt:.2f} s/step "
+          f"{F / dt / 1e12:.2f} TFLOP/s, epilogue avg {rec['epilogue_avg_s'] * 1e3:.3f} ms",
+          file=sys.stderr, flush=True)
+    return rec
 
 
 def run_df(args, bqc, x, dev, prec, hr, F, naux, seed):
@@ -504,6 +535,8 @@ def main():
     }
     if args.df and x is not None:
         out["density_fitting"] = run_df(args, bqc, x, dev, head, hr, F, naux, seed)
+    if args.fock:
+        out["fock_ov"] = run_fock(args, bqc, dev, o, v, head, F, seed, form)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(x, args.cpu_seconds)
     line = json.dumps(out)
