@@ -137,11 +137,12 @@ def run_df(args, bqc, x, dev, prec, hr, F, naux, seed):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources that define the contraction kernel (its file and
-    the shared header): traffic counters taken on other sources are stale."""
+    """Hash of the sources that define the contraction kernel and its launch
+    (its file, the shared header and the solve driver, which sets the triples
+    per launch): traffic counters taken on other sources are stale."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2502_17963_amd", "csrc")
-    for f in ("bqc_internal.h", "kernels_gemm.hip"):
+    for f in ("bqc_internal.h", "kernels_gemm.hip", "solve.hip"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
