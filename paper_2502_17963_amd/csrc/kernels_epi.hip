@@ -92,7 +92,6 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     // one per loop trip.
     // phase 0 loads: singles-term factors (27 8x8 blocks of (ov|ov)) and t1
     constexpr int NG = (27 * T2 + E_THREADS - 1) / E_THREADS;
-    const int occ[3] = {i, j, k};
     double gv[NG];
 #pragma unroll
     for (int n = 0; n < NG; ++n) {
