@@ -295,7 +295,6 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
                                                               int ntile_w, int per_xcd) {
     constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, NVEC = G::NVEC, WB = G::WB;
     typedef Mode<PREC> M;
-    typedef typename M::E E;
     typedef typename M::Acc Acc;
     typedef typename M::HT HT;
     constexpr int KC = M::KC;
