@@ -193,6 +193,13 @@ int64_t bqc_t_num_triples(int32_t nocc);
  * or -1 for invalid arguments. */
 int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision);
 
+/* bqc_t_footprint for a formulation (BQC_FORM_*) and a reference with
+ * (fock != 0) or without an f_ov block: the loop over virtual triples also
+ * holds transposed copies of t1, (ia|jb) and, with f_ov, t2 and f_ov.
+ * -1 for invalid arguments (sizes < 1, unknown precision or formulation,
+ * FP8 with BQC_FORM_VIRTUAL). */
+int64_t bqc_t_footprint_ex(int32_t nocc, int32_t nvir, int32_t precision, int32_t formulation, int32_t fock);
+
 /* ---------------------------------------------------------------- serving
  * A server owns one device, a memory budget and a scheduler thread.  Each
  * request is one independent (T) solve (an embedding fragment).  Requests

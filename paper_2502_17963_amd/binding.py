@@ -98,6 +98,8 @@ def lib():
             L.bqc_t_num_triples.restype = ctypes.c_int64
             L.bqc_t_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
             L.bqc_t_footprint.restype = ctypes.c_int64
+            L.bqc_t_footprint_ex.argtypes = [ctypes.c_int32] * 5
+            L.bqc_t_footprint_ex.restype = ctypes.c_int64
             L.bqc_last_error.argtypes = []
             L.bqc_last_error.restype = ctypes.c_char_p
             L.bqc_version.argtypes = []
@@ -140,8 +142,11 @@ def num_triples(nocc: int) -> int:
     return int(lib().bqc_t_num_triples(nocc))
 
 
-def footprint(nocc: int, nvir: int, precision="fp64") -> int:
-    return int(lib().bqc_t_footprint(nocc, nvir, _prec(precision)))
+def footprint(nocc: int, nvir: int, precision="fp64", formulation="occupied", fock=False) -> int:
+    """Device bytes one solve holds (bqc_t_footprint_ex), -1 for invalid arguments."""
+    if formulation not in FORMULATIONS:
+        return -1
+    return int(lib().bqc_t_footprint_ex(nocc, nvir, _prec(precision), FORMULATIONS[formulation], 1 if fock else 0))
 
 
 def _prec(p):

@@ -386,6 +386,16 @@ int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision) {
     return workspace_bytes(nocc, nvir, precision) + input_bytes(nocc, nvir);
 }
 
+int64_t bqc_t_footprint_ex(int32_t nocc, int32_t nvir, int32_t precision, int32_t formulation, int32_t fock) {
+    if (nocc < 1 || nvir < 1 || precision < 0 || precision > 3) return -1;
+    if (formulation != BQC_FORM_OCCUPIED && formulation != BQC_FORM_VIRTUAL) return -1;
+    const int form = formulation == BQC_FORM_VIRTUAL ? FORM_VIR : FORM_OCC;
+    if (form == FORM_VIR && precision == BQC_PREC_FP8) return -1;
+    int64_t in = input_bytes(nocc, nvir);
+    if (fock) in += (int64_t)nocc * nvir * 8 + 256;
+    return workspace_bytes(nocc, nvir, precision, form, fock != 0) + in;
+}
+
 const char* bqc_last_error(void) { return g_last_error.c_str(); }
 
 int32_t bqc_version(void) { return 100; }

@@ -39,6 +39,21 @@ def test_footprint_grows_with_size_and_shrinks_with_precision():
     assert f32 > 0
 
 
+def test_footprint_of_formulations():
+    L = bqc.lib()
+    o, v = 32, 300
+    base = L.bqc_t_footprint(o, v, 2)
+    assert L.bqc_t_footprint_ex(o, v, 2, 0, 0) == base
+    vir = bqc.footprint(o, v, "bf16x3", formulation="virtual")
+    # the virtual loop adds transposes of t1 and (ia|jb) (o^2 v^2 doubles)
+    assert vir - base >= 8 * (o * v) ** 2
+    fock = bqc.footprint(o, v, "bf16x3", formulation="virtual", fock=True)
+    assert fock - vir >= 8 * (o * v) ** 2  # and of t2 with an f_ov block
+    assert bqc.footprint(o, v, "bf16x3", fock=True) - base == 8 * o * v + 256
+    for args in [(0, v, 2, 0, 0), (o, 0, 2, 0, 0), (o, v, 9, 0, 0), (o, v, 2, 2, 0), (o, v, 3, 1, 0)]:
+        assert L.bqc_t_footprint_ex(*args) == -1, args
+
+
 def _call(o, v, arrays, E=True, precision=0, triple_range=(0, 0), formulation=0):
     ptrs = [None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrays]
     e = ctypes.c_double(123.0)
