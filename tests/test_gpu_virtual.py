@@ -168,3 +168,18 @@ def test_many_occupied_fp64(o, v, naux, seed):
     for prec, tol in (("fp64", FP64_REL), ("bf16x3", 1e-6)):
         e = bqc.t_energy(o, v, *x.arrays(), precision=prec, formulation="virtual")
         assert abs(e - ref) <= tol * abs(ref), (prec, e, ref)
+
+
+@pytest.mark.parametrize("form,fock", [("occupied", False), ("occupied", True), ("virtual", False), ("virtual", True)])
+def test_footprint_bounds_the_solve(form, fock):
+    """bqc_t_footprint_ex is an upper bound of what a host-input solve holds
+    (its stats), within 1 %."""
+    bqc = _bqc()
+    o, v, naux, seed = 7, 45, 150, 2
+    x = make_inputs(o, v, naux, seed)
+    f = np.random.default_rng(5).normal(0.0, 0.02, (o, v)) if fock else None
+    _, ex = bqc.t_energy(o, v, *x.arrays(), precision="bf16x3", stats=True, fock_ov=f, formulation=form)
+    held = ex["stats"]["footprint_bytes"]
+    bound = bqc.footprint(o, v, "bf16x3", formulation=form, fock=fock)
+    print(f"footprint {form} fock={fock}: solve {held} bound {bound}", flush=True)
+    assert held <= bound <= 1.01 * held
