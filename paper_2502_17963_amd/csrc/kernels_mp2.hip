@@ -49,8 +49,10 @@ __global__ __launch_bounds__(M_THREADS) void mp2_kernel(const double* __restrict
         for (int y = 0; y < 2; ++y) k1[x][y] = k2[x][y] = d4{0, 0, 0, 0};
 
     const int64_t ov = (int64_t)o * v;
-    for (int Q0 = 0; Q0 < naux; Q0 += M_K) {
-        double r[16];
+    // the strips of step Q0 + M_K are loaded into registers while step Q0 is
+    // contracted from LDS
+    double r[16];
+    auto load = [&](int Q0) {
 #pragma unroll
         for (int n = 0; n < 16; ++n) {
             const int idx = tid + M_THREADS * n;  // < 4 * 16 * 64
@@ -58,10 +60,14 @@ __global__ __launch_bounds__(M_THREADS) void mp2_kernel(const double* __restrict
             const int occ = s < 2 ? i : j, col = (s & 1 ? B0 : A0) + m, Q = Q0 + k;
             r[n] = (Q < naux && col < v) ? b_ov[(int64_t)Q * ov + (int64_t)occ * v + col] : 0.0;
         }
-        __syncthreads();
+    };
+    load(0);
+    for (int Q0 = 0; Q0 < naux; Q0 += M_K) {
+        __syncthreads();  // the previous step's fragment reads are done
 #pragma unroll
         for (int n = 0; n < 16; ++n) lds[tid + M_THREADS * n] = r[n];
         __syncthreads();
+        if (Q0 + M_K < naux) load(Q0 + M_K);
 #pragma unroll
         for (int st = 0; st < M_K / 4; ++st) {
             const int k = 4 * st + fg;  // contraction index of this lane in the 16x16x4 step
