@@ -183,3 +183,29 @@ def test_footprint_bounds_the_solve(form, fock):
     bound = bqc.footprint(o, v, "bf16x3", formulation=form, fock=fock)
     print(f"footprint {form} fock={fock}: solve {held} bound {bound}", flush=True)
     assert held <= bound <= 1.01 * held
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_all_options_together(prec):
+    """Loop over virtual triples with density fitting, an f_ov block, device
+    inputs and a triple share at once: per-triple energies of the share
+    against the oracle's."""
+    import torch
+    bqc = _bqc()
+    o, v, naux, seed = 5, 23, 80, 6
+    print(f"case virtual all options {prec}", flush=True)
+    x = make_inputs(o, v, naux, seed)
+    f = np.random.default_rng(1000 + seed).normal(0.0, 0.02, (o, v))
+    e_ref, terms = vl.t_energy_virtual_loop(*x.arrays(), return_triples=True, fock_ov=f)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+           for a in make_df_inputs(o, v, naux, seed)]
+    f_dev = torch.from_numpy(f).to("cuda:0")
+    n = bqc.num_triples(v)
+    b, e = n // 4, 3 * n // 4
+    es, ex = bqc.t_energy_df(o, v, naux, *dev, precision=prec, triple_energies=True, triple_range=(b, e),
+                             fock_ov=f_dev, formulation="virtual")
+    torch.cuda.synchronize()
+    got, ref = ex["triples"][b:e], np.array(terms[b:e])
+    tol_triple, tol_sum = (1e-10, 1e-10) if prec == "fp64" else (1e-5, 1e-6)
+    assert np.max(np.abs(got - ref)) <= tol_triple * np.max(np.abs(ref))
+    assert abs(es - float(np.sum(ref))) <= tol_sum * abs(float(np.sum(ref)))
