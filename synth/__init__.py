@@ -35,6 +35,7 @@ import numpy as np
 __all__ = [
     "TInputs",
     "draw_factors",
+    "direct_sum_inputs",
     "make_inputs",
     "serving_stream",
     "CONFIGS",
@@ -109,6 +110,37 @@ def make_inputs(nocc: int, nvir: int, naux: int, seed: int) -> TInputs:
     return TInputs(nocc, nvir, eps_o, eps_v, t1, t2,
                    np.ascontiguousarray(ovvv), np.ascontiguousarray(ooov),
                    np.ascontiguousarray(ovov))
+
+
+def direct_sum_inputs(shapes):
+    """Inputs of several non-interacting fragments as one system: each
+    fragment (nocc, nvir, naux, seed) keeps the draw of make_inputs, its DF
+    factors live on its own Q range and its own orbitals, and cross singles
+    are zero.  Orbital order: the occupied orbitals of every fragment, then
+    the virtuals of every fragment.  Returns the seven FP64 ABI arrays."""
+    draws = [draw_factors(o, v, q, s) for (o, v, q, s) in shapes]
+    no = sum(o for (o, _, _, _) in shapes)
+    nv = sum(v for (_, v, _, _) in shapes)
+    nq = sum(q for (_, _, q, _) in shapes)
+    n = no + nv
+    b = np.zeros((nq, n, n))
+    t1 = np.zeros((no, nv))
+    eps_o, eps_v = [], []
+    q0, o0, v0 = 0, 0, 0
+    for (o, v, q, _), (bf, eo, ev, t1f) in zip(shapes, draws):
+        idx = list(range(o0, o0 + o)) + list(range(no + v0, no + v0 + v))
+        b[np.ix_(range(q0, q0 + q), idx, idx)] = bf
+        t1[o0:o0 + o, v0:v0 + v] = t1f
+        eps_o.append(eo)
+        eps_v.append(ev)
+        q0, o0, v0 = q0 + q, o0 + o, v0 + v
+    ovvv, ooov, ovov = _integrals(b, no)
+    eps_o, eps_v = np.concatenate(eps_o), np.concatenate(eps_v)
+    den = (eps_o[:, None, None, None] + eps_o[None, :, None, None]
+           - eps_v[None, None, :, None] - eps_v[None, None, None, :])
+    t2 = np.ascontiguousarray(ovov.transpose(0, 2, 1, 3)) / den
+    return (eps_o, eps_v, t1, t2, np.ascontiguousarray(ovvv), np.ascontiguousarray(ooov),
+            np.ascontiguousarray(ovov))
 
 
 def make_df_inputs(nocc: int, nvir: int, naux: int, seed: int):

@@ -15,8 +15,7 @@ import pytest
 
 import oracle.closed_shell as cs
 from oracle import spinorb_t_energy, t_energy, w_tensor
-from synth import draw_factors, make_inputs
-from synth import _integrals as integrals_from_factors
+from synth import direct_sum_inputs, make_inputs
 
 
 def _rel(a, b):
@@ -123,37 +122,10 @@ def test_orbital_relabelling_invariance():
     assert _rel(e1, e0) < 1e-13
 
 
-def _direct_sum(fa, fb):
-    """Inputs of two fragments whose DF factors live on disjoint Q ranges
-    and disjoint orbitals, with zero cross singles."""
-    (ba, oa_eps, va_eps, t1a, oa, va) = fa
-    (bb, ob_eps, vb_eps, t1b, ob, vb) = fb
-    no, nv = oa + ob, va + vb
-    qa, qb = ba.shape[0], bb.shape[0]
-    n = no + nv
-    # orbital order: occupied of A, occupied of B, virtuals of A, virtuals of B
-    ia = list(range(oa)) + list(range(no, no + va))
-    ib = list(range(oa, no)) + list(range(no + va, n))
-    b = np.zeros((qa + qb, n, n))
-    b[np.ix_(range(qa), ia, ia)] = ba
-    b[np.ix_(range(qa, qa + qb), ib, ib)] = bb
-    ovvv, ooov, ovov = integrals_from_factors(b, no)
-    eps_o = np.concatenate([oa_eps, ob_eps])
-    eps_v = np.concatenate([va_eps, vb_eps])
-    t1 = np.zeros((no, nv))
-    t1[:oa, :va] = t1a
-    t1[oa:, va:] = t1b
-    den = eps_o[:, None, None, None] + eps_o[None, :, None, None] - eps_v[None, None, :, None] - eps_v[None, None, None, :]
-    t2 = ovov.transpose(0, 2, 1, 3) / den
-    return eps_o, eps_v, t1, t2, ovvv, ooov, ovov
-
-
 def test_size_extensivity_two_fragments():
-    fa = draw_factors(2, 4, 8, 21) + (2, 4)
-    fb = draw_factors(3, 5, 9, 22) + (3, 5)
     ea = t_energy(*make_inputs(2, 4, 8, 21).arrays())
     eb = t_energy(*make_inputs(3, 5, 9, 22).arrays())
-    eab = t_energy(*_direct_sum(fa, fb))
+    eab = t_energy(*direct_sum_inputs([(2, 4, 8, 21), (3, 5, 9, 22)]))
     assert _rel(eab, ea + eb) < 1e-12
 
 
