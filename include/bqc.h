@@ -69,14 +69,29 @@ int bqc_t_energy(int32_t nocc, int32_t nvir,
                  double* E_T);
 
 /* Options of bqc_t_energy_ex.  A zero-initialised struct means: FP64,
- * device 0, host inputs, library stream, no per-triple output. */
+ * device 0, host inputs, library stream, no per-triple output.  The first
+ * four fields are the boundary's base options (precision, device, input
+ * residency, stream); the fields after them extend it, so a caller that
+ * knows only the first four and zero-fills the rest gets the defaults. */
 typedef struct {
     int32_t precision;        /* bqc_precision */
     int32_t device;           /* HIP device ordinal */
     int32_t inputs_on_device; /* 1: the seven input pointers are device pointers on `device`,
                                  readable in stream order on `stream` */
-    int32_t timing;           /* 1: record per-kernel HIP events and fill the kernel fields of stats */
     void*   stream;           /* hipStream_t to run on, or NULL for the library's stream of `device` */
+    /* ---- extensions (zero = default) ---- */
+    int32_t timing;           /* 1: record per-kernel HIP events and fill the kernel fields of stats */
+    int32_t formulation;      /* BQC_FORM_OCCUPIED (0, default): the loop runs over unique occupied
+                                 triples i <= j <= k with tensors over the virtuals.  BQC_FORM_VIRTUAL:
+                                 the loop runs over unique virtual triples a <= b <= c with tensors over
+                                 the occupied indices (the loop order of paper section 2.4.2); E_T is the
+                                 same sum taken in the other order.  With BQC_FORM_VIRTUAL "triple" in
+                                 triple_energies, triple_begin and triple_end means a unique virtual
+                                 triple (a <= b <= c, lexicographic, a = b = c skipped;
+                                 bqc_t_num_triples(nvir) of them), stats->flops is 12 n_triples nocc^3
+                                 (nocc + nvir), and BQC_PREC_FP8 is rejected with BQC_EINVAL.  Any
+                                 other value: BQC_EINVAL.  A solve whose loop has more than 2^31 - 1
+                                 unique triples (nvir > 2343 here) is rejected with BQC_EINVAL. */
     double* triple_energies;  /* NULL, or a HOST array of bqc_t_num_triples(nocc) doubles that receives
                                  the per-triple energies e_ijk in unique-triple order (with a triple
                                  range, only the entries of the range are written) */
@@ -95,33 +110,24 @@ typedef struct {
                                  energies eps); adds the f_ov t2 part of the disconnected triples (paper
                                  Eqs. 5 and 7: x_k F_ck), folded into V as f_ia t_jk^bc + f_jb t_ik^ac +
                                  f_kc t_ij^ab.  Must be finite (host) else BQC_EINVAL. */
-    int32_t formulation;      /* BQC_FORM_OCCUPIED (0, default): the loop runs over unique occupied
-                                 triples i <= j <= k with tensors over the virtuals.  BQC_FORM_VIRTUAL:
-                                 the loop runs over unique virtual triples a <= b <= c with tensors over
-                                 the occupied indices (the loop order of paper section 2.4.2); E_T is the
-                                 same sum taken in the other order.  With BQC_FORM_VIRTUAL "triple" in
-                                 triple_energies, triple_begin and triple_end means a unique virtual
-                                 triple (a <= b <= c, lexicographic, a = b = c skipped;
-                                 bqc_t_num_triples(nvir) of them), stats->flops is 12 n_triples nocc^3
-                                 (nocc + nvir), and BQC_PREC_FP8 is rejected with BQC_EINVAL.  Any
-                                 other value: BQC_EINVAL.  A solve whose loop has more than 2^31 - 1
-                                 unique triples (nvir > 2343 here) is rejected with BQC_EINVAL. */
 } bqc_t_opts;
 
 #define BQC_FORM_OCCUPIED 0
 #define BQC_FORM_VIRTUAL  1
 
-/* Per-solve measurements.  Times are seconds. */
+/* Per-solve measurements.  Times are seconds.  The first six fields are the
+ * boundary's base statistics; the fields after them extend it. */
 typedef struct {
     double   queue_s;      /* serving: submit -> admission */
     double   upload_s;     /* host -> device copies (0 for device inputs) */
-    double   prepare_s;    /* layout and precision conversion of the inputs (HIP events) */
     double   gpu_s;        /* first kernel start -> final reduction end (HIP events) */
     double   total_s;      /* wall time of the call (serving: submit -> completion) */
     double   flops;        /* algorithmic flops 12 * n_triples * v^3 * (v + o) */
+    uint64_t footprint_bytes; /* device memory the solve held */
+    /* ---- extensions ---- */
+    double   prepare_s;    /* layout and precision conversion of the inputs (HIP events) */
     double   gemm_s;       /* timing=1: summed duration of the contraction kernel launches */
     double   epilogue_s;   /* timing=1: summed duration of the epilogue kernel launches */
-    uint64_t footprint_bytes; /* device memory the solve held */
     int32_t  gemm_launches;
     int32_t  epilogue_launches;
     int32_t  precision;
@@ -270,6 +276,14 @@ const char* bqc_last_error(void);
 
 /* ABI version: major * 10000 + minor * 100 + patch. */
 int32_t bqc_version(void);
+
+/* HIP versions (major * 10000000 + minor * 100000 + patch): *compiled = the
+ * HIP headers the library was built with, *runtime = hipRuntimeGetVersion()
+ * of the HIP runtime the process has loaded (the library binds to the one
+ * runtime of the process, e.g. the one a framework loaded first).  Either
+ * pointer may be NULL.  Returns BQC_OK, or BQC_EDEVICE if the runtime cannot
+ * report its version. */
+int bqc_hip_versions(int32_t* compiled, int32_t* runtime);
 
 #ifdef __cplusplus
 }

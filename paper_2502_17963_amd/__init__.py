@@ -13,10 +13,11 @@ from .binding import (  # noqa: F401
     lib,
     mp2_energy_df,
     num_triples,
+    runtime_versions,
     t_energy,
     t_energy_df,
     t_energy_plain,
 )
 
 __all__ = ["BqcError", "Server", "PRECISIONS", "footprint", "header_functions", "last_error", "lib",
-           "mp2_energy_df", "num_triples", "t_energy", "t_energy_df", "t_energy_plain"]
+           "mp2_energy_df", "num_triples", "runtime_versions", "t_energy", "t_energy_df", "t_energy_plain"]

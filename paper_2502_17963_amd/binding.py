@@ -26,22 +26,24 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 class TOpts(ctypes.Structure):
+    # include/bqc.h: the four base options first, then the extensions
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("inputs_on_device", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("triple_energies", _dp),
-                ("triple_begin", ctypes.c_int64), ("triple_end", ctypes.c_int64),
-                ("fock_ov", _dp), ("formulation", ctypes.c_int32)]
+                ("inputs_on_device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("timing", ctypes.c_int32), ("formulation", ctypes.c_int32),
+                ("triple_energies", _dp), ("triple_begin", ctypes.c_int64),
+                ("triple_end", ctypes.c_int64), ("fock_ov", _dp)]
 
 
 FORMULATIONS = {"occupied": 0, "virtual": 1}
 
 
 class TStats(ctypes.Structure):
+    # include/bqc.h: the six base statistics first, then the extensions
     _fields_ = [("queue_s", ctypes.c_double), ("upload_s", ctypes.c_double),
-                ("prepare_s", ctypes.c_double), ("gpu_s", ctypes.c_double),
-                ("total_s", ctypes.c_double), ("flops", ctypes.c_double),
-                ("gemm_s", ctypes.c_double), ("epilogue_s", ctypes.c_double),
-                ("footprint_bytes", ctypes.c_uint64), ("gemm_launches", ctypes.c_int32),
+                ("gpu_s", ctypes.c_double), ("total_s", ctypes.c_double),
+                ("flops", ctypes.c_double), ("footprint_bytes", ctypes.c_uint64),
+                ("prepare_s", ctypes.c_double), ("gemm_s", ctypes.c_double),
+                ("epilogue_s", ctypes.c_double), ("gemm_launches", ctypes.c_int32),
                 ("epilogue_launches", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("n_triples", ctypes.c_int32)]
 
@@ -104,6 +106,8 @@ def lib():
             L.bqc_last_error.restype = ctypes.c_char_p
             L.bqc_version.argtypes = []
             L.bqc_version.restype = ctypes.c_int32
+            L.bqc_hip_versions.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+            L.bqc_hip_versions.restype = ctypes.c_int
             if hasattr(L, "bqc_server_create"):
                 L.bqc_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
                 L.bqc_server_create.restype = ctypes.c_int
@@ -136,6 +140,15 @@ def last_error() -> str:
 def _check(rc):
     if rc != OK:
         raise BqcError(rc, last_error())
+
+
+def runtime_versions() -> dict:
+    """HIP version the library was compiled with and of the runtime the
+    process has loaded (bqc_hip_versions)."""
+    c, r = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = lib().bqc_hip_versions(ctypes.byref(c), ctypes.byref(r))
+    return {"compiled": c.value, "runtime": r.value if rc == OK else None,
+            "match": rc == OK and c.value // 100000 == r.value // 100000}
 
 
 def num_triples(nocc: int) -> int:

@@ -398,6 +398,15 @@ int64_t bqc_t_footprint_ex(int32_t nocc, int32_t nvir, int32_t precision, int32_
 
 const char* bqc_last_error(void) { return g_last_error.c_str(); }
 
-int32_t bqc_version(void) { return 100; }
+int32_t bqc_version(void) { return 200; }
+
+int bqc_hip_versions(int32_t* compiled, int32_t* runtime) {
+    if (compiled) *compiled = HIP_VERSION;
+    if (!runtime) return BQC_OK;
+    int rv = 0;
+    if (hipRuntimeGetVersion(&rv) != hipSuccess) return fail(BQC_EDEVICE, "hipRuntimeGetVersion failed");
+    *runtime = rv;
+    return BQC_OK;
+}
 
 }  // extern "C"

@@ -30,19 +30,6 @@
 
 namespace bqc {
 
-int operand_bytes(int precision) {
-    switch (precision) {
-        case 0: return 8;
-        case 1: return 4;
-        case 2: return 4;  // hi + lo bf16
-        case 3: return 1;
-        default: throw Error(-1, "unknown precision");
-    }
-}
-int hbuf_bytes(int precision) { return precision == 0 ? 8 : 4; }
-int chunk_elems(int precision) { return 128 / operand_bytes(precision); }
-int kpad_of(int precision) { return precision == 3 ? 128 : KPAD; }
-
 namespace {
 
 constexpr int P_THREADS = 256;
@@ -274,27 +261,6 @@ void launch_df_ovvv(const DevInputs& in, int P0, int np, hipStream_t st) {
 
 }  // namespace
 
-int df_block_planes(int o, int v) {
-    const int64_t v3 = (int64_t)v * v * v;
-    const int64_t cap = (int64_t)1 << 26;  // 512 MB of FP64 scratch
-    int64_t b = cap / std::max<int64_t>(v3, 1);
-    b = std::max<int64_t>(1, std::min<int64_t>(b, o));
-    return (int)b;
-}
-int64_t df_scratch_elems(int o, int v) { return (int64_t)df_block_planes(o, v) * v * v * v; }
-
-
-Sizes factor_sizes(int o, int v, int precision) {
-    const int kp = kpad_of(precision);
-    Sizes s;
-    s.Kv = ceil_div(v, kp) * kp;
-    s.Ko = ceil_div(o, kp) * kp;
-    s.m_ovvv = (int64_t)o * v;
-    s.m_t2 = (int64_t)o * o;
-    s.m_t2l = (int64_t)o * v;
-    s.m_hoo = (int64_t)o * o;
-    return s;
-}
 
 namespace {
 
@@ -411,18 +377,6 @@ void prepare_fp8(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
 
 }  // namespace
 
-int64_t prepare_bytes(int precision, int o, int v) {
-    const Sizes z = factor_sizes(o, v, precision);
-    const int eb = operand_bytes(precision);
-    int64_t b = align256((size_t)z.m_ovvv * v * z.Kv * eb) + align256((size_t)z.m_t2 * v * z.Kv * eb) +
-                align256((size_t)z.m_t2l * v * z.Ko * eb) + align256((size_t)z.m_hoo * v * z.Ko * eb);
-    if (precision == 3) {  // one scale byte per 32 contraction elements
-        b += align256((size_t)z.m_ovvv * v * z.Kv / 32) + align256((size_t)z.m_t2 * v * z.Kv / 32) +
-             align256((size_t)z.m_t2l * v * z.Ko / 32) + align256((size_t)z.m_hoo * v * z.Ko / 32);
-    }
-    return b;
-}
-
 void launch_prepare(int precision, const DevInputs& in, void* ws, Operands* ops, hipStream_t st, int form) {
     if (form == FORM_VIR) {
         switch (precision) {
@@ -476,13 +430,6 @@ void launch_aux(const double* src, double* dst, int64_t n, int kind, int o, int 
 }
 
 }  // namespace
-
-int64_t vir_aux_bytes(int o, int v, bool fock) {
-    const int64_t ov = (int64_t)o * v;
-    int64_t b = align256(v * 8) + align256(o * 8) + align256(ov * 8) + align256(ov * ov * 8);
-    if (fock) b += align256(ov * ov * 8) + align256(ov * 8);
-    return b;
-}
 
 VirAux launch_vir_aux(const DevInputs& in, void* aux, hipStream_t st) {
     const int o = in.o, v = in.v;

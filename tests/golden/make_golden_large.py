@@ -1,0 +1,90 @@
+"""Write the FP64 oracle's whole solve of the large fragment.
+
+Calls only the FP64 oracle (``oracle.closed_shell.triple_energy``, one call
+per unique occupied triple, exactly as ``oracle.t_energy`` makes them) and
+the seeded input generator.  The triples are spread over worker processes
+(each with one BLAS thread); the per-triple energies are collected in
+unique-triple order and summed with math.fsum, as ``oracle.t_energy`` does.
+
+Workload: nocc = 32, nvir = 300, naux = 1000, seed 0 (5952 unique triples,
+6.4e14 flops; one to two hours on eight host cores).  Output:
+tests/golden/large_fragment_seed0.json with E_T, every per-triple energy and
+a fingerprint of the generated inputs.  Run from the repository root:
+
+    python tests/golden/make_golden_large.py [--workers N]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+# one BLAS thread per worker process (set before numpy loads its BLAS)
+for _k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_k] = "1"
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import multiprocessing as mp  # noqa: E402
+
+from oracle.closed_shell import triple_energy, triple_table  # noqa: E402
+from synth import make_inputs  # noqa: E402
+
+SHAPE = (32, 300, 1000, 0)
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large_fragment_seed0.json")
+
+_X = None  # inputs, inherited by the forked workers
+
+
+def fingerprint(x) -> str:
+    """sha256 over the bytes of the orbital energies, t1 and a strided
+    sample of every other array (identifies the generated inputs)."""
+    h = hashlib.sha256()
+    for a in (x.eps_o, x.eps_v, x.t1):
+        h.update(a.tobytes())
+    for a in (x.t2, x.ovvv, x.ooov, x.ovov):
+        h.update(a.reshape(-1)[::4099].tobytes())
+    return h.hexdigest()
+
+
+def _one(args):
+    idx, (i, j, k, m) = args
+    return idx, triple_energy(i, j, k, m, *_X.arrays())
+
+
+def main():
+    global _X
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workers", type=int, default=max(1, (os.cpu_count() or 2) - 2))
+    a = ap.parse_args()
+    o, v, naux, seed = SHAPE
+    t0 = time.time()
+    _X = make_inputs(o, v, naux, seed)
+    table = triple_table(o)
+    print(f"inputs in {time.time() - t0:.0f} s; {len(table)} triples on {a.workers} workers", flush=True)
+    terms = [None] * len(table)
+    ctx = mp.get_context("fork")
+    done = 0
+    with ctx.Pool(a.workers) as pool:
+        for idx, e in pool.imap_unordered(_one, list(enumerate(table)), chunksize=1):
+            terms[idx] = e
+            done += 1
+            if done % 100 == 0 or done == len(table):
+                el = time.time() - t0
+                print(f"{done}/{len(table)} triples at {el:.0f} s "
+                      f"(eta {el / done * (len(table) - done):.0f} s)", flush=True)
+    e_t = math.fsum(terms)
+    rec = {"nocc": o, "nvir": v, "naux": naux, "seed": seed, "generator": "synth.make_inputs",
+           "oracle": "oracle.closed_shell.triple_energy per unique triple, math.fsum over triples",
+           "input_fingerprint": fingerprint(_X), "E_T": e_t, "triples": terms}
+    with open(OUT, "w") as f:
+        json.dump(rec, f)
+        f.write("\n")
+    print(f"E_T = {e_t!r}; wrote {OUT} after {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,6 +4,7 @@ The library loads, exports every function include/bqc.h declares, and the
 argument checks that precede any device work return the documented codes.
 """
 import ctypes
+import os
 
 import numpy as np
 import pytest
@@ -207,3 +208,57 @@ def test_server_argument_checks():
     x = make_inputs(2, 3, 6, 0)
     ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in x.arrays()]
     assert L.bqc_t_submit(None, 2, 3, *ptrs, ctypes.byref(t)) == binding.EINVAL
+
+
+# Offsets of the boundary's base fields (the first four options and the
+# first six statistics), in the order and C layout the boundary fixes; the
+# extension fields follow them.
+_BASE_OPTS = [("precision", 0), ("device", 4), ("inputs_on_device", 8), ("stream", 16)]
+_BASE_STATS = [("queue_s", 0), ("upload_s", 8), ("gpu_s", 16), ("total_s", 24), ("flops", 32),
+               ("footprint_bytes", 40)]
+
+
+def _c_layout(tmp_path):
+    """offsetof / sizeof of every field of bqc_t_opts and bqc_t_stats, from a
+    C program compiled against include/bqc.h."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    fields = {"bqc_t_opts": [f for f, _ in binding.TOpts._fields_],
+              "bqc_t_stats": [f for f, _ in binding.TStats._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bqc.h"', "int main(void) {"]
+    for st, names in fields.items():
+        lines.append(f'printf("{st} sizeof %zu\\n", sizeof({st}));')
+        for n in names:
+            lines.append(f'printf("{st} {n} %zu\\n", offsetof({st}, {n}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-I" + inc, str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    lay = {}
+    for line in out.splitlines():
+        st, name, val = line.split()
+        lay[(st, name)] = int(val)
+    return lay
+
+
+def test_struct_base_fields_lead_in_boundary_order(tmp_path):
+    lay = _c_layout(tmp_path)
+    for name, off in _BASE_OPTS:
+        assert lay[("bqc_t_opts", name)] == off, name
+    for name, off in _BASE_STATS:
+        assert lay[("bqc_t_stats", name)] == off, name
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    lay = _c_layout(tmp_path)
+    for cls, st in ((binding.TOpts, "bqc_t_opts"), (binding.TStats, "bqc_t_stats")):
+        assert ctypes.sizeof(cls) == lay[(st, "sizeof")]
+        for name, _ in cls._fields_:
+            assert getattr(cls, name).offset == lay[(st, name)], (st, name)
