@@ -118,6 +118,8 @@ struct bqc_server {
     std::vector<hipStream_t> sides;  // epilogue stream of each slot
     std::vector<double*> pinned;
     bool stop = false;
+    int callers = 0;                 // threads inside submit/poll/wait (destroy waits for them)
+    std::condition_variable cv_idle;
     uint64_t next_ticket = 1;
     hipStream_t check_stream = nullptr;  // reads device orbital energies at submit
     std::mutex check_mu;
@@ -287,6 +289,17 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
     return BQC_OK;
 }
 
+}  // namespace
+
+// Threads inside submit/poll/wait of the server (host-side tests use it to
+// destroy a server while waiters are known to be blocked).
+int server_callers(bqc_server* s) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->callers;
+}
+
+namespace {
+
 int destroy_impl(bqc_server* s) {
     if (!s) return fail(BQC_EINVAL, "null server");
     {
@@ -300,7 +313,13 @@ int destroy_impl(bqc_server* s) {
     }
     s->cv_work.notify_all();
     for (auto& th : s->slots) th.join();
-    s->cv_done.notify_all();
+    {
+        // every request is Done now: wake the waiters and let every thread
+        // still inside an entry point of this server leave before freeing it
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.notify_all();
+        s->cv_idle.wait(lk, [&] { return s->callers == 0; });
+    }
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
@@ -316,9 +335,24 @@ int destroy_impl(bqc_server* s) {
     return BQC_OK;
 }
 
+// Counts a thread inside an entry point of the server (destroy waits until
+// none is left).  Constructed and destroyed without s->mu held.
+struct Caller {
+    bqc_server* s;
+    explicit Caller(bqc_server* srv) : s(srv) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        ++s->callers;
+    }
+    ~Caller() {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (--s->callers == 0) s->cv_idle.notify_all();
+    }
+};
+
 int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7], bool dev_in,
                 uint64_t* ticket) {
     if (!s || !ticket) return fail(BQC_EINVAL, "null argument");
+    Caller in_call(s);
     int rc = validate(o, v, src[0], src[1], src[2], src[3], src[4], src[5], src[6], !dev_in);
     if (rc != BQC_OK) return rc;
     if (dev_in) {  // orbital energies are checked from a host copy, read on the server's own stream
@@ -369,11 +403,21 @@ int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7],
 
 int poll_impl(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats, bool wait) {
     if (!s) return fail(BQC_EINVAL, "null server");
+    Caller in_call(s);
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return fail(BQC_ENOTFOUND, "unknown or consumed ticket");
+    if (wait) {
+        // the ticket is looked up again on every wake-up: another thread may
+        // have consumed it (and freed its request) meanwhile
+        s->cv_done.wait(lk, [&] {
+            auto f = s->reqs.find(ticket);
+            return f == s->reqs.end() || f->second->state == St::Done;
+        });
+        it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return fail(BQC_ENOTFOUND, "ticket consumed by another thread");
+    }
     Request* r = it->second;
-    if (wait) s->cv_done.wait(lk, [&] { return r->state == St::Done; });
     if (r->state != St::Done) return BQC_PENDING;
     const int rc = r->rc;
     if (rc == BQC_OK) {

@@ -41,6 +41,10 @@
 #include "bqc.h"
 #include "mock_hip.h"
 
+namespace bqc {
+int server_callers(bqc_server* s);  // server.cpp: threads inside an entry point
+}
+
 namespace {
 
 double expected_energy(int o, const std::vector<double>& eo) {
@@ -285,17 +289,19 @@ int run_stream(const char* path, int direct, int max_req) {
 // --------------------------------------------------------------- consumers
 int run_consumers() {
     bqc_server_cfg cfg{};
-    cfg.mem_budget_bytes = (uint64_t)64 << 20;
+    cfg.mem_budget_bytes = (uint64_t)4 << 30;  // two of the (8, 60) requests at a time
     cfg.max_inflight = 2;
     bqc_server* s = nullptr;
-    if (bqc_server_create(&cfg, &s) != 0) return 1;
+    if (bqc_server_create(&cfg, &s) != 0) { std::printf("create failed: %s\n", bqc_last_error()); return 1; }
     int bad = 0;
     for (int round = 0; round < 50; ++round) {
         const int o = 3 + round % 4, v = 12 + round % 9;
         std::vector<double> eo = occ_energies(o, round), ev(v, 0.7), z((size_t)o * v * v * v + o * o * v * v, 0.0);
         uint64_t t = 0;
-        if (bqc_t_submit(s, o, v, eo.data(), ev.data(), z.data(), z.data(), z.data(), z.data(), z.data(), &t) != 0)
+        if (bqc_t_submit(s, o, v, eo.data(), ev.data(), z.data(), z.data(), z.data(), z.data(), z.data(), &t) != 0) {
+            std::printf("submit failed: %s\n", bqc_last_error());
             return 1;
+        }
         std::atomic<int> ok{0}, nf{0}, other{0};
         auto consume = [&](bool wait) {
             double e = 0;
@@ -319,19 +325,24 @@ int run_consumers() {
         std::vector<double> eo = occ_energies(8, 1), ev(60, 0.9), z((size_t)8 * 60 * 60 * 60 + 8 * 8 * 60 * 60, 0.0);
         std::vector<uint64_t> ts(12);
         for (auto& t : ts)
-            if (bqc_t_submit(s, 8, 60, eo.data(), ev.data(), z.data(), z.data(), z.data(), z.data(), z.data(), &t) != 0)
+            if (bqc_t_submit(s, 8, 60, eo.data(), ev.data(), z.data(), z.data(), z.data(), z.data(), z.data(), &t) != 0) {
+                std::printf("submit failed: %s\n", bqc_last_error());
                 return 1;
+            }
         std::atomic<int> started{0};
         std::vector<std::thread> ws;
-        std::atomic<int> wrong{0};
+        std::atomic<int> wrong{0}, done_waiting{0};
         for (uint64_t t : ts)
             ws.emplace_back([&, t] {
                 started++;
                 double e = 0;
                 const int rc = bqc_t_wait(s, t, &e, nullptr);
+                done_waiting++;
                 if (rc != BQC_OK && rc != BQC_ESHUTDOWN && rc != BQC_ENOTFOUND) wrong++;
             });
         while (started.load() < (int)ts.size()) std::this_thread::yield();
+        // every waiter is inside bqc_t_wait (or already returned) before the destroy
+        while (bqc::server_callers(s) + done_waiting.load() < (int)ts.size()) std::this_thread::yield();
         bqc_server_destroy(s);
         for (auto& w : ws) w.join();
         if (wrong.load()) { std::printf("destroy with waiters: %d unexpected codes\n", wrong.load()); ++bad; }

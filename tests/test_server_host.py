@@ -1,10 +1,19 @@
 """The server's host logic (queue, admission by footprint, arena, tickets,
-poll/wait) under ThreadSanitizer and AddressSanitizer, on the CPU.
+poll/wait) under ThreadSanitizer, AddressSanitizer and
+UndefinedBehaviorSanitizer, on the CPU.
 
-csrc/server.cpp is compiled with g++ against stand-ins for the HIP calls and
-the solve entry points it uses (tests/host_server/mock_runtime.cpp); a
-driver submits 900 requests from six threads and checks every result.  No
-GPU code is built or run.
+Two harnesses, both compiled with g++ against stand-ins for the HIP runtime
+(no GPU code is built or run):
+  * stress.cpp + mock_runtime.cpp: csrc/server.cpp alone, with the solve
+    entry points stubbed; six threads submit 900 requests;
+  * serving_stress.cpp + mock_hip.cpp + mock_kernels.cpp: the real server,
+    C ABI and solve driver (triple tables, workspace layout, explicitly built
+    graphs, events, two-stream pipeline) on an emulated runtime whose
+    kernels check every device range they touch.  Modes: six client threads;
+    the serving stream's own 256 fragment shapes with a submitter that
+    allocates, fills, submits, polls, frees and empties its allocator cache
+    concurrently with the server's slots; several threads consuming one
+    ticket and a destroy while waiters are blocked.
 """
 import os
 import shutil
@@ -19,18 +28,70 @@ HERE = os.path.join(ROOT, "tests", "host_server")
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"),
                                 reason="needs g++ and the HIP headers")
 
+FLAGS = {"thread": ["-fsanitize=thread"],
+         "address": ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=all"]}
+ENV = {"TSAN_OPTIONS": "halt_on_error=1", "ASAN_OPTIONS": "halt_on_error=1:detect_leaks=0",
+       "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"}
+
+
+def _compile(sources, exe, sanitizer):
+    cmd = ["g++", "-std=c++17", "-O1", "-g", *FLAGS[sanitizer], "-D__HIP_PLATFORM_AMD__",
+           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + SRC, *sources, "-o", exe,
+           "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+
+
+def _run(cmd, timeout=900):
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=timeout, env=dict(os.environ, **ENV))
+    out = r.stdout + r.stderr
+    assert "WARNING: ThreadSanitizer" not in out and "ERROR: AddressSanitizer" not in out, out[-4000:]
+    assert "runtime error:" not in out and "MOCK-HIP FAULT" not in out, out[-4000:]
+    assert r.returncode == 0, out[-4000:]
+    return out
+
 
 @pytest.mark.parametrize("sanitizer", ["thread", "address"])
 def test_server_host_logic_under_sanitizer(sanitizer, tmp_path):
     exe = str(tmp_path / f"stress_{sanitizer}")
-    cmd = ["g++", "-std=c++17", "-O1", "-g", f"-fsanitize={sanitizer}", "-D__HIP_PLATFORM_AMD__",
-           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + SRC,
-           os.path.join(SRC, "server.cpp"), os.path.join(HERE, "mock_runtime.cpp"),
-           os.path.join(HERE, "stress.cpp"), "-o", exe, "-lpthread"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-3000:]
-    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="halt_on_error=1")
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "done 900 bad 0" in out, out[-4000:]
-    assert "WARNING: ThreadSanitizer" not in out and "ERROR: AddressSanitizer" not in out
+    _compile([os.path.join(SRC, "server.cpp"), os.path.join(HERE, "mock_runtime.cpp"),
+              os.path.join(HERE, "stress.cpp")], exe, sanitizer)
+    assert "done 900 bad 0" in _run([exe])
+
+
+@pytest.fixture(scope="module", params=["address", "thread"])
+def serving_exe(request, tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("serving") / f"serving_stress_{request.param}")
+    _compile(["-x", "c++", os.path.join(SRC, "solve.hip"), "-x", "none", os.path.join(SRC, "server.cpp"),
+              os.path.join(SRC, "abi.cpp"), os.path.join(SRC, "sizes.cpp"), os.path.join(HERE, "mock_hip.cpp"),
+              os.path.join(HERE, "mock_kernels.cpp"), os.path.join(HERE, "serving_stress.cpp")], exe,
+             request.param)
+    return request.param, exe
+
+
+def test_serving_client_threads(serving_exe):
+    _, exe = serving_exe
+    assert "threads: done 360 bad 0" in _run([exe, "threads"])
+
+
+def test_serving_shared_ticket_and_destroy_with_waiters(serving_exe):
+    """Two or three threads consume one ticket (exactly one gets the result,
+    the others BQC_ENOTFOUND, and no waiter reads a freed request); then the
+    server is destroyed while twelve waiters are blocked inside bqc_t_wait."""
+    _, exe = serving_exe
+    assert "consumers: bad 0" in _run([exe, "consumers"])
+
+
+def test_serving_stream_shapes(serving_exe, tmp_path):
+    """The serving stream's fragment shapes (nocc 8..40, nvir up to 400; real
+    triple tables, batch sizes and graphs of up to 64 batches) with the
+    benchmark's submit / poll / free / empty-cache pattern, graphs and direct
+    launches (ThreadSanitizer: the first 128 fragments)."""
+    from synth import serving_stream
+    san, exe = serving_exe
+    shapes = tmp_path / "shapes.txt"
+    shapes.write_text("".join(f"{s['nocc']} {s['nvir']}\n" for s in serving_stream(256)))
+    n = 256 if san == "address" else 128
+    for direct in ("0", "1"):
+        out = _run([exe, "stream", str(shapes), direct, str(n)])
+        assert f"stream: done {n} bad 0" in out, out[-2000:]
