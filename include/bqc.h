@@ -48,6 +48,7 @@ extern "C" {
 #define BQC_EDEVICE   -3   /* HIP runtime or kernel failure */
 #define BQC_ENOTFOUND -4   /* unknown or already consumed ticket */
 #define BQC_ESHUTDOWN -5   /* the server is shutting down */
+#define BQC_ECANCELED -6   /* the request was cancelled before it ran (bqc_t_cancel) */
 
 /* Arithmetic of the contractions (Eq. 2).  The energy denominator, the
  * per-triple energy and the sum over triples are FP64 in every mode. */
@@ -207,13 +208,27 @@ int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision);
 int64_t bqc_t_footprint_ex(int32_t nocc, int32_t nvir, int32_t precision, int32_t formulation, int32_t fock);
 
 /* ---------------------------------------------------------------- serving
- * A server owns one device, a memory budget and a scheduler thread.  Each
- * request is one independent (T) solve (an embedding fragment).  Requests
- * are admitted in arrival order as soon as the in-flight count and the
- * memory budget allow; admitted requests run concurrently on the device.
- * A request's result is bitwise identical to bqc_t_energy_ex at the same
- * precision on the same device: its decomposition and reduction order depend
- * only on (nocc, nvir, precision).
+ * Continuous batching of independent (T) solves.  The paper's embedding
+ * layer splits a system into fragments (clusters) whose correlated
+ * calculations are independent problems of uneven size (section 2.5), and
+ * the cost of the small ones is dominated by launch overhead unless their
+ * work is batched (section 2.4.2); a server keeps many such solves in
+ * flight on one device.
+ *
+ * A server owns one device, a device memory arena of mem_budget_bytes
+ * (allocated once at creation; the serving loop itself never allocates) and
+ * max_inflight slot threads, each with its own streams.  A request is one
+ * solve; an idle slot admits the oldest queued request whose footprint
+ * (workspace, plus the inputs when they are host arrays) fits the arena
+ * (smaller requests may overtake a waiting one a bounded number of times),
+ * uploads it and runs its launch sequence, so admitted requests run
+ * concurrently on the device while new ones keep arriving.  A request's
+ * result is bitwise identical to bqc_t_energy_ex at the same precision on
+ * the same device: its decomposition and reduction order depend only on
+ * (nocc, nvir, precision).  A failing request (device error, failed host
+ * allocation) returns its error at its terminal poll; its memory returns to
+ * the arena after its streams have drained, and other requests are not
+ * affected.
  */
 typedef struct bqc_server bqc_server;
 
@@ -268,8 +283,16 @@ int bqc_t_submit_ex(bqc_server* s, int32_t nocc, int32_t nvir,
  */
 int bqc_t_poll(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats);
 
-/* Blocking variant of bqc_t_poll (waits until the ticket is terminal). */
+/* Blocking variant of bqc_t_poll (waits until the ticket is terminal).  If
+ * another thread consumes the ticket meanwhile, returns BQC_ENOTFOUND. */
 int bqc_t_wait(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats);
+
+/* Cancels a queued request: it is removed from the queue and never runs; its
+ * terminal poll returns BQC_ECANCELED.  Returns BQC_OK (cancelled, or the
+ * request had already finished: its poll tells which), BQC_PENDING (it is
+ * running and will complete normally), BQC_ENOTFOUND (unknown or consumed
+ * ticket).  Thread-safe. */
+int bqc_t_cancel(bqc_server* s, uint64_t ticket);
 
 /* Thread-local message of the calling thread's last non-OK return. */
 const char* bqc_last_error(void);

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbqc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bqc.h")
 
-OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOTFOUND, ESHUTDOWN = 0, 1, -1, -2, -3, -4, -5
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOTFOUND, ESHUTDOWN, ECANCELED = 0, 1, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp8": 3}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -123,6 +123,8 @@ def lib():
                 L.bqc_t_poll.restype = ctypes.c_int
                 L.bqc_t_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64, _dp, ctypes.POINTER(TStats)]
                 L.bqc_t_wait.restype = ctypes.c_int
+                L.bqc_t_cancel.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+                L.bqc_t_cancel.restype = ctypes.c_int
             _lib = L
         return _lib
 
@@ -363,6 +365,15 @@ class Server:
 
     def wait(self, ticket):
         return self._finish(lib().bqc_t_wait, ticket)
+
+    def cancel(self, ticket) -> bool:
+        """bqc_t_cancel: True if the request was cancelled before it ran (or had
+        already finished; its poll tells which), False if it is running."""
+        rc = lib().bqc_t_cancel(self._h, ticket)
+        if rc == PENDING:
+            return False
+        _check(rc)
+        return True
 
     def close(self):
         if self._h:

@@ -98,7 +98,12 @@ struct Request {
     size_t bytes = 0, off = 0;
     int bypassed = 0;
     bool dev_in = false;  // inputs are device pointers read in place
+    int fault_stage = 0, fault_code = 0;  // injected failure (host-side tests)
 };
+
+// Stages at which a host-side test can make one request fail.
+constexpr int FAULT_AT_ADMISSION = 1;  // right after its memory is carved out, before any upload
+constexpr int FAULT_AFTER_SOLVE = 2;   // after its kernels have run, before its result is read
 
 }  // namespace
 }  // namespace bqc
@@ -119,6 +124,7 @@ struct bqc_server {
     std::vector<double*> pinned;
     bool stop = false;
     int callers = 0;                 // threads inside submit/poll/wait (destroy waits for them)
+    std::map<uint64_t, std::pair<int, int>> faults;  // host-side tests: ticket -> (stage, code)
     std::condition_variable cv_idle;
     uint64_t next_ticket = 1;
     hipStream_t check_stream = nullptr;  // reads device orbital energies at submit
@@ -162,6 +168,7 @@ int run_request(bqc_server* s, Request* r, hipStream_t st, hipStream_t side, dou
     const Plan plan = make_plan(o, v, s->precision);
     SolveStats ss;
     enqueue_solve(plan, in, ws, nullptr, st, side, false, &ss, s->graphs);
+    if (r->fault_stage == FAULT_AFTER_SOLVE) throw Error(r->fault_code, "injected failure after the solve");
     BQC_HIP(hipMemcpyAsync(pinned, workspace_energy(ws, o, v, s->precision), sizeof(double),
                            hipMemcpyDeviceToHost, st));
     BQC_HIP(hipStreamSynchronize(st));
@@ -184,6 +191,12 @@ Request* admit_locked(bqc_server* s) {
         size_t off = 0;
         if (s->arena->alloc(r->bytes, &off)) {
             r->off = off;
+            auto f = s->faults.find(r->ticket);
+            if (f != s->faults.end()) {
+                r->fault_stage = f->second.first;
+                r->fault_code = f->second.second;
+                s->faults.erase(f);
+            }
             for (size_t b = 0; b < q; ++b) s->queue[b]->bypassed++;
             s->queue.erase(s->queue.begin() + q);
             return r;
@@ -214,15 +227,24 @@ void slot_main(bqc_server* s, int idx) {
         int rc;
         std::string err;
         try {
+            if (r->fault_stage == FAULT_AT_ADMISSION) throw Error(r->fault_code, "injected failure at admission");
             rc = run_request(s, r, st, side, pinned);
         } catch (const Error& e) {
             rc = e.code;
             err = e.what();
+        } catch (const std::bad_alloc&) {
+            rc = BQC_ENOMEM;
+            err = "host allocation failed";
         } catch (const std::exception& e) {
             rc = BQC_EDEVICE;
             err = e.what();
         }
-        if (rc != BQC_OK) (void)hipStreamSynchronize(st);
+        // a failed request may still have work in flight on either stream:
+        // its memory goes back to the arena only once both have drained
+        if (rc != BQC_OK) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamSynchronize(side);
+        }
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->arena->release(r->off, r->bytes);
@@ -296,6 +318,14 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
 int server_callers(bqc_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     return s->callers;
+}
+
+// Host-side tests: the request with this ticket (submitted already or in
+// the future; tickets count up from 1) fails with `code` at `stage`
+// (FAULT_AT_ADMISSION or FAULT_AFTER_SOLVE) instead of completing.
+void server_inject_fault(bqc_server* s, uint64_t ticket, int stage, int code) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->faults[ticket] = {stage, code};
 }
 
 namespace {
@@ -401,6 +431,30 @@ int submit_impl(bqc_server* s, int32_t o, int32_t v, const double* const src[7],
     return BQC_OK;
 }
 
+// Cancels a queued request: it leaves the queue, never runs, and its
+// terminal status is BQC_ECANCELED.  A running request is not interrupted.
+int cancel_impl(bqc_server* s, uint64_t ticket) {
+    if (!s) return fail(BQC_EINVAL, "null server");
+    Caller in_call(s);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return fail(BQC_ENOTFOUND, "unknown or consumed ticket");
+        Request* r = it->second;
+        if (r->state == St::Running) return BQC_PENDING;
+        if (r->state == St::Done) return BQC_OK;  // finished (or failed) already: the poll tells which
+        auto q = std::find(s->queue.begin(), s->queue.end(), r);
+        if (q != s->queue.end()) s->queue.erase(q);
+        r->rc = BQC_ECANCELED;
+        r->err = "request cancelled before admission";
+        r->stats.queue_s = std::chrono::duration<double>(clk::now() - r->t_submit).count();
+        r->state = St::Done;
+    }
+    s->cv_work.notify_all();  // the head of the queue may have changed
+    s->cv_done.notify_all();
+    return BQC_OK;
+}
+
 int poll_impl(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats, bool wait) {
     if (!s) return fail(BQC_EINVAL, "null server");
     Caller in_call(s);
@@ -481,6 +535,10 @@ int bqc_t_poll(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats) 
 
 int bqc_t_wait(bqc_server* s, uint64_t ticket, double* E_T, bqc_t_stats* stats) {
     return guarded_srv([&] { return poll_impl(s, ticket, E_T, stats, true); });
+}
+
+int bqc_t_cancel(bqc_server* s, uint64_t ticket) {
+    return guarded_srv([&] { return cancel_impl(s, ticket); });
 }
 
 }  // extern "C"

@@ -16,6 +16,10 @@
 //       allocator's cache after every completion (device frees while the
 //       server's slots run); at the end three fragments are solved alone
 //       with bqc_t_energy_ex and compared with their served energies.
+//   serving_stress faults <direct_launch 0|1>
+//       failure isolation: some requests fail at admission (BQC_ENOMEM) or
+//       after their solve (BQC_EDEVICE) by injection, others are cancelled
+//       while queued; every other request's energy is unchanged.
 //   serving_stress consumers
 //       two threads consume the same ticket at once (wait and poll); one
 //       gets the result, the other BQC_ENOTFOUND; then the server is
@@ -43,6 +47,7 @@
 
 namespace bqc {
 int server_callers(bqc_server* s);  // server.cpp: threads inside an entry point
+void server_inject_fault(bqc_server* s, uint64_t ticket, int stage, int code);  // server.cpp
 }
 
 namespace {
@@ -286,6 +291,69 @@ int run_stream(const char* path, int direct, int max_req) {
     return fails != 0;
 }
 
+// --------------------------------------------------------------- faults
+int run_faults(int direct) {
+    bqc_server_cfg cfg{};
+    cfg.mem_budget_bytes = (uint64_t)6 << 30;  // a few requests at a time: the others queue
+    cfg.max_inflight = 3;
+    cfg.precision = BQC_PREC_BF16X3;
+    cfg.direct_launch = direct;
+    bqc_server* s = nullptr;
+    if (bqc_server_create(&cfg, &s) != 0) { std::printf("create failed: %s\n", bqc_last_error()); return 1; }
+    constexpr int N = 90;
+    // tickets count up from 1: inject before submitting
+    for (int n = 0; n < N; ++n) {
+        const uint64_t t = (uint64_t)n + 1;
+        if (n % 7 == 3) bqc::server_inject_fault(s, t, 1, BQC_ENOMEM);
+        if (n % 7 == 5) bqc::server_inject_fault(s, t, 2, BQC_EDEVICE);
+    }
+    struct Job { int o, v; std::vector<double> eo, ev, z; uint64_t t; int cancel_rc; };
+    std::vector<Job> jobs(N);
+    for (int n = 0; n < N; ++n) {
+        Job& j = jobs[n];
+        j.o = 4 + n % 9;
+        j.v = 40 + 7 * (n % 5);
+        j.eo = occ_energies(j.o, n);
+        j.ev.assign(j.v, 0.6);
+        j.z.assign((size_t)j.o * j.v * j.v * j.v + (size_t)j.o * j.o * j.v * j.v, 0.0);
+        const double* z = j.z.data();
+        if (bqc_t_submit(s, j.o, j.v, j.eo.data(), j.ev.data(), z, z, z, z, z, &j.t) != 0 ||
+            j.t != (uint64_t)n + 1) {
+            std::printf("submit %d failed: %s\n", n, bqc_last_error());
+            return 1;
+        }
+        j.cancel_rc = n % 11 == 4 ? bqc_t_cancel(s, j.t) : 99;
+    }
+    int bad = 0, cancelled = 0, enomem = 0, edevice = 0, ok = 0;
+    for (int n = N - 1; n >= 0; --n) {  // consume in reverse order
+        Job& j = jobs[n];
+        double e = 0;
+        const int rc = bqc_t_wait(s, j.t, &e, nullptr);
+        int want = BQC_OK;
+        if (j.cancel_rc == BQC_OK) want = BQC_ECANCELED;  // cancelled while queued
+        else if (n % 7 == 3) want = BQC_ENOMEM;
+        else if (n % 7 == 5) want = BQC_EDEVICE;
+        if (j.cancel_rc != 99 && j.cancel_rc != BQC_OK && j.cancel_rc != BQC_PENDING) want = -100;
+        const bool good = rc == want && (rc != BQC_OK || e == expected_energy(j.o, j.eo));
+        if (!good) {
+            std::printf("faults: request %d rc %d (want %d) energy %.17g (want %.17g) cancel %d\n", n, rc, want, e,
+                        expected_energy(j.o, j.eo), j.cancel_rc);
+            ++bad;
+        }
+        cancelled += rc == BQC_ECANCELED;
+        enomem += rc == BQC_ENOMEM;
+        edevice += rc == BQC_EDEVICE;
+        ok += rc == BQC_OK;
+        double e2 = 0;
+        if (bqc_t_poll(s, j.t, &e2, nullptr) != BQC_ENOTFOUND) ++bad;  // consumed
+    }
+    if (bqc_t_cancel(s, 12345) != BQC_ENOTFOUND) ++bad;
+    bqc_server_destroy(s);
+    std::printf("faults: ok %d cancelled %d enomem %d edevice %d bad %d\n", ok, cancelled, enomem, edevice, bad);
+    std::fflush(stdout);
+    return bad != 0 || cancelled == 0 || enomem == 0 || edevice == 0;
+}
+
 // --------------------------------------------------------------- consumers
 int run_consumers() {
     bqc_server_cfg cfg{};
@@ -359,6 +427,7 @@ int main(int argc, char** argv) {
     const std::string mode = argv[1];
     if (mode == "threads") return run_threads();
     if (mode == "consumers") return run_consumers();
+    if (mode == "faults" && argc >= 3) return run_faults(std::atoi(argv[2]));
     if (mode == "stream" && argc >= 4) return run_stream(argv[2], std::atoi(argv[3]), argc > 4 ? std::atoi(argv[4]) : 0);
     std::printf("bad arguments\n");
     return 2;

@@ -262,3 +262,4 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert ctypes.sizeof(cls) == lay[(st, "sizeof")]
         for name, _ in cls._fields_:
             assert getattr(cls, name).offset == lay[(st, name)], (st, name)
+

@@ -139,3 +139,30 @@ def test_request_of_many_graphs_matches_direct_solve():
         t = srv.submit(o, v, *x)
         e_srv, st = srv.wait(t)
     assert e_srv == e_direct
+
+
+def test_cancel_queued_request():
+    """One slot: the requests behind the first are queued; cancelling one of
+    them removes it (its terminal poll is BQC_ECANCELED) and every other
+    request's energy is the one it has alone."""
+    bqc = _bqc()
+    shapes = [(6, 30, 120, 301), (5, 24, 80, 302), (4, 20, 60, 303), (6, 28, 100, 304)]
+    xs = [make_inputs(*s) for s in shapes]
+    alone = [bqc.t_energy(s[0], s[1], *x.arrays(), precision="bf16x3") for s, x in zip(shapes, xs)]
+    print("case serving cancel", flush=True)
+    with bqc.Server(precision="bf16x3", max_inflight=1, mem_budget_bytes=1 << 30) as srv:
+        tickets = [srv.submit(s[0], s[1], *x.arrays()) for s, x in zip(shapes, xs)]
+        cancelled = srv.cancel(tickets[3])
+        for k, t in enumerate(tickets):
+            if k == 3 and cancelled:
+                try:
+                    e, _ = srv.wait(t)  # it had finished before the cancel
+                except bqc.BqcError as err:
+                    assert err.code == -6
+                    continue
+            else:
+                e, _ = srv.wait(t)
+            assert e == alone[k], (shapes[k], e, alone[k])
+        with pytest.raises(bqc.BqcError) as ei:
+            srv.cancel(tickets[0])
+        assert ei.value.code == -4

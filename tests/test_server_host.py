@@ -95,3 +95,15 @@ def test_serving_stream_shapes(serving_exe, tmp_path):
     for direct in ("0", "1"):
         out = _run([exe, "stream", str(shapes), direct, str(n)])
         assert f"stream: done {n} bad 0" in out, out[-2000:]
+
+
+def test_serving_failure_isolation(serving_exe):
+    """Requests made to fail at admission (BQC_ENOMEM) or after their solve
+    (BQC_EDEVICE) by injection, and requests cancelled while queued
+    (BQC_ECANCELED), among 90 requests on three slots: every other request's
+    energy is unchanged, every ticket is consumed once, graphs and direct
+    launches."""
+    _, exe = serving_exe
+    for direct in ("0", "1"):
+        out = _run([exe, "faults", direct])
+        assert "bad 0" in out and "faults: ok" in out, out[-2000:]
