@@ -261,3 +261,16 @@ def make_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:
     if factors:
         return tuple(a.contiguous() for a in (eps_o, eps_v, t1, t2, f_ov, f_vv, ooov, ovov))
     return tuple(a.contiguous() for a in (eps_o, eps_v, t1, t2, ovvv, ooov, ovov))
+
+
+def fingerprint(x) -> str:
+    """sha256 over the bytes of the orbital energies, t1 and a strided sample
+    (every 4099th element) of t2, (ia|bc), ooov and ovov of generated inputs
+    x: identifies the inputs a stored result was computed from."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (x.eps_o, x.eps_v, x.t1):
+        h.update(a.tobytes())
+    for a in (x.t2, x.ovvv, x.ooov, x.ovov):
+        h.update(a.reshape(-1)[::4099].tobytes())
+    return h.hexdigest()

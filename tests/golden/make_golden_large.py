@@ -14,7 +14,6 @@ a fingerprint of the generated inputs.  Run from the repository root:
     python tests/golden/make_golden_large.py [--workers N]
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -31,23 +30,12 @@ sys.path.insert(0, ROOT)
 import multiprocessing as mp  # noqa: E402
 
 from oracle.closed_shell import triple_energy, triple_table  # noqa: E402
-from synth import make_inputs  # noqa: E402
+from synth import fingerprint, make_inputs  # noqa: E402
 
 SHAPE = (32, 300, 1000, 0)
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large_fragment_seed0.json")
 
 _X = None  # inputs, inherited by the forked workers
-
-
-def fingerprint(x) -> str:
-    """sha256 over the bytes of the orbital energies, t1 and a strided
-    sample of every other array (identifies the generated inputs)."""
-    h = hashlib.sha256()
-    for a in (x.eps_o, x.eps_v, x.t1):
-        h.update(a.tobytes())
-    for a in (x.t2, x.ovvv, x.ooov, x.ovov):
-        h.update(a.reshape(-1)[::4099].tobytes())
-    return h.hexdigest()
 
 
 def _one(args):

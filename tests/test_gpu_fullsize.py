@@ -1,18 +1,33 @@
 """Parity at the benchmarked size (nocc=32, nvir=300, naux=1000, seed 0).
 
-The whole solve is too large for the oracle, so the GPU's per-triple
-energies are compared with the oracle's on a seeded sample of unique
-triples (including triples with repeated indices), in the launch
-configuration the benchmark times.  Totals of the mixed-precision modes are
-compared with the FP64 GPU total (itself checked triple by triple).
+The oracle's whole solve of this workload is stored
+(tests/golden/large_fragment_seed0.json, written by
+tests/golden/make_golden_large.py, which calls only the oracle and the
+generator): the GPU's FP64 per-triple energies are compared with it triple
+by triple and in total, and the mixed-precision totals with its total, in
+the launch configuration the benchmark times.  A seeded sample of triples
+is also recomputed by the oracle at test time.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 from oracle.closed_shell import triple_energy, triple_table
-from synth import CONFIGS, make_inputs
+from synth import CONFIGS, fingerprint, make_inputs
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "large_fragment_seed0.json")
+
+
+def _golden(x):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("the oracle's whole solve of the large fragment has not been stored")
+    rec = json.load(open(GOLDEN))
+    assert rec["input_fingerprint"] == fingerprint(x), "the generator no longer makes the stored inputs"
+    return rec
 
 
 @pytest.fixture(scope="module")
@@ -43,6 +58,33 @@ def test_fp64_sampled_triples_match_oracle(large):
         print(f"triple {n} ({i},{j},{k}) gpu={trip[n]:.15e} oracle={ref:.15e}", flush=True)
         assert abs(trip[n] - ref) <= 1e-10 * abs(ref)
     assert abs(float(np.sum(trip)) - e64) <= 1e-12 * abs(e64)
+
+
+def test_fp64_every_triple_matches_stored_oracle(large):
+    """Every one of the 5952 per-triple energies at 1e-10 relative (of the
+    largest), and E_T at 1e-10 relative, against the oracle's whole solve."""
+    bqc, x, dev, e64, trip = large
+    rec = _golden(x)
+    ref = np.array(rec["triples"])
+    assert ref.shape == trip.shape
+    worst = np.max(np.abs(trip - ref)) / np.max(np.abs(ref))
+    rel = abs(e64 - rec["E_T"]) / abs(rec["E_T"])
+    print(f"stored oracle E_T={rec['E_T']:.15e} gpu={e64:.15e} rel={rel:.3e} worst triple {worst:.3e}", flush=True)
+    assert worst <= 1e-10
+    assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_totals_against_stored_oracle(large, prec):
+    import torch
+    bqc, x, dev, e64, _ = large
+    rec = _golden(x)
+    e = bqc.t_energy(x.nocc, x.nvir, *dev, precision=prec)
+    torch.cuda.synchronize()
+    rel = abs(e - rec["E_T"]) / abs(rec["E_T"])
+    print(f"{prec}: E={e:.12e} oracle={rec['E_T']:.12e} rel={rel:.3e} dE={abs(e - rec['E_T']) * 1e6:.3e} uEh",
+          flush=True)
+    assert rel <= 1e-6
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
