@@ -207,6 +207,43 @@ int64_t bqc_t_footprint(int32_t nocc, int32_t nvir, int32_t precision);
  * FP8 with BQC_FORM_VIRTUAL). */
 int64_t bqc_t_footprint_ex(int32_t nocc, int32_t nvir, int32_t precision, int32_t formulation, int32_t fock);
 
+/* ------------------------------------------------------- no device allocation
+ * For callers that cannot allocate device memory (code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * solve of bqc_t_energy_ex with device-resident inputs whose workspace is a
+ * fixed device array of the library, BQC_NOALLOC_SCRATCH_BYTES bytes on each
+ * device the library runs on, held from its first use until the process
+ * ends.  The call allocates no device memory and creates no stream or event.
+ *
+ * opts is required and must have inputs_on_device = 1 (else BQC_EINVAL); the
+ * seven input pointers (and fock_ov, if set) are device pointers on
+ * opts->device, read in stream order on opts->stream (NULL: the device's
+ * null stream).  precision, formulation, triple_begin/triple_end, fock_ov
+ * and triple_energies (a HOST array, as in bqc_t_energy_ex) work as in
+ * bqc_t_energy_ex; timing is ignored.  Returns after the stream has drained,
+ * with *E_T bitwise equal to bqc_t_energy_ex's for the same arguments (the
+ * kernels and every summation order are the same; only the number of triples
+ * per launch may be smaller).  stats (may be NULL): flops, footprint_bytes
+ * (bytes of the array used), precision and n_triples; the time fields are 0.
+ *
+ * A shape whose workspace does not fit the array, even at one triple per
+ * launch, is rejected with BQC_ENOMEM (bqc_t_noalloc_batch returns 0 for it);
+ * other errors as bqc_t_energy_ex.  Every call on one device uses the same
+ * array: calls that overlap in time on one device race and must be
+ * serialised by the caller.
+ */
+#define BQC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int bqc_t_energy_noalloc(int32_t nocc, int32_t nvir,
+                         const double* eps_o, const double* eps_v,
+                         const double* t1, const double* t2,
+                         const double* ovvv, const double* ooov, const double* ovov,
+                         const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats);
+
+/* Triples per launch bqc_t_energy_noalloc uses for this shape (0: the shape
+ * does not fit the array; -1: invalid arguments, as bqc_t_footprint_ex). */
+int64_t bqc_t_noalloc_batch(int32_t nocc, int32_t nvir, int32_t precision, int32_t formulation, int32_t fock);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of independent (T) solves.  The paper's embedding
  * layer splits a system into fragments (clusters) whose correlated

@@ -12,12 +12,15 @@ from .binding import (  # noqa: F401
     last_error,
     lib,
     mp2_energy_df,
+    noalloc_batch,
     num_triples,
     runtime_versions,
     t_energy,
     t_energy_df,
+    t_energy_noalloc,
     t_energy_plain,
 )
 
 __all__ = ["BqcError", "Server", "PRECISIONS", "footprint", "header_functions", "last_error", "lib",
-           "mp2_energy_df", "num_triples", "runtime_versions", "t_energy", "t_energy_df", "t_energy_plain"]
+           "mp2_energy_df", "noalloc_batch", "num_triples", "runtime_versions", "t_energy", "t_energy_df",
+           "t_energy_noalloc", "t_energy_plain"]

@@ -102,6 +102,11 @@ def lib():
             L.bqc_t_footprint.restype = ctypes.c_int64
             L.bqc_t_footprint_ex.argtypes = [ctypes.c_int32] * 5
             L.bqc_t_footprint_ex.restype = ctypes.c_int64
+            L.bqc_t_energy_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, *seven,
+                                               ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
+            L.bqc_t_energy_noalloc.restype = ctypes.c_int
+            L.bqc_t_noalloc_batch.argtypes = [ctypes.c_int32] * 5
+            L.bqc_t_noalloc_batch.restype = ctypes.c_int64
             L.bqc_last_error.argtypes = []
             L.bqc_last_error.restype = ctypes.c_char_p
             L.bqc_version.argtypes = []
@@ -256,6 +261,37 @@ def t_energy(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64
     rc = lib().bqc_t_energy_ex(nocc, nvir, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
     del keep
     return _finish(rc, e, st, etrip, ntrip, triple_energies, stats, timing)
+
+
+def t_energy_noalloc(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov, precision="fp64", device=0,
+                     triple_energies=False, stream=None, stats=False, triple_range=None, fock_ov=None,
+                     formulation="occupied"):
+    """E_T through bqc_t_energy_noalloc (device tensors only; the library's
+    fixed device array is the workspace).  Arguments and results as
+    t_energy."""
+    arrays = (eps_o, eps_v, t1, t2, ovvv, ooov, ovov)
+    ptrs, opts, keep = _solve_opts(arrays, precision, device, False, stream, triple_range, fock_ov,
+                                   formulation)
+    if not opts.inputs_on_device:
+        raise ValueError("bqc_t_energy_noalloc takes device tensors")
+    ntrip = num_triples(nvir if formulation == "virtual" else nocc)
+    etrip = None
+    if triple_energies:
+        etrip = np.zeros(max(ntrip, 1))
+        opts.triple_energies = etrip.ctypes.data_as(_dp)
+    e = ctypes.c_double(0.0)
+    st = TStats()
+    rc = lib().bqc_t_energy_noalloc(nocc, nvir, *ptrs, ctypes.byref(opts), ctypes.byref(e), ctypes.byref(st))
+    del keep
+    return _finish(rc, e, st, etrip, ntrip, triple_energies, stats, False)
+
+
+def noalloc_batch(nocc, nvir, precision="fp64", formulation="occupied", fock=False) -> int:
+    """Triples per launch of bqc_t_energy_noalloc (0: does not fit its array)."""
+    if formulation not in FORMULATIONS:
+        return -1
+    return int(lib().bqc_t_noalloc_batch(nocc, nvir, _prec(precision), FORMULATIONS[formulation],
+                                         1 if fock else 0))
 
 
 def t_energy_df(nocc, nvir, naux, eps_o, eps_v, t1, t2, b_ov, b_vv, ooov, ovov, precision="fp64",

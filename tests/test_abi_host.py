@@ -263,3 +263,15 @@ def test_ctypes_structs_match_the_header(tmp_path):
         for name, _ in cls._fields_:
             assert getattr(cls, name).offset == lay[(st, name)], (st, name)
 
+
+def test_noalloc_batch_query():
+    """bqc_t_noalloc_batch: small shapes fit the 64 MiB array with the
+    library's own batch size or a smaller one, large ones do not fit, and
+    invalid arguments give -1."""
+    import paper_2502_17963_amd as bqc
+    bqc.lib()
+    assert bqc.noalloc_batch(6, 30, "fp64") == 50       # every triple in one launch
+    assert 1 <= bqc.noalloc_batch(10, 80, "bf16x3") < 210
+    assert bqc.noalloc_batch(32, 300, "bf16x3") == 0     # (ia|bc) alone exceeds the array
+    assert bqc.noalloc_batch(6, 30, "fp8", "virtual") == -1
+    assert bqc.noalloc_batch(0, 30, "fp64") == -1
