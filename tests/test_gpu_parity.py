@@ -195,3 +195,25 @@ def test_triple_shares_add_up_to_the_solve(prec):
         assert abs(es - float(np.sum(ex["triples"][b:e]))) <= 1e-14 * max(abs(es), 1e-300)
         parts.append(es)
     assert abs(sum(parts) - e_all) <= 1e-13 * abs(e_all)
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(4, 130, 440, 11), (3, 200, 670, 12), (3, 100, 340, 13)])
+def test_medium_shapes_every_precision(o, v, naux, seed):
+    """Shapes whose contraction uses wave tiles of 4 x 4 or 5 x 5 blocks
+    (one ragged tile at nvir = 130, two of 4 x 4 at nvir = 200 and 100):
+    every per-triple energy in FP64 at 1e-10 of the oracle's, FP32 and
+    split-BF16x3 at 1e-6 relative in total."""
+    from oracle import t_energy as oracle_t_energy
+    bqc = _bqc()
+    x = make_inputs(o, v, naux, seed)
+    ref, ref_t = oracle_t_energy(*x.arrays(), return_triples=True)
+    ref_t = np.array(ref_t)
+    for prec, tol in [("fp64", FP64_REL), ("fp32", 1e-6), ("bf16x3", 1e-6)]:
+        print(f"case medium o={o} v={v} {prec}", flush=True)
+        e, ex = bqc.t_energy(o, v, *x.arrays(), precision=prec, triple_energies=True)
+        got = ex["triples"]
+        print(f"  rel {abs(e - ref) / abs(ref):.3e} worst triple {np.max(np.abs(got - ref_t)) / np.max(np.abs(ref_t)):.3e}",
+              flush=True)
+        assert abs(e - ref) <= tol * abs(ref), (prec, e, ref)
+        if prec == "fp64":
+            assert np.max(np.abs(got - ref_t)) <= FP64_REL * np.max(np.abs(ref_t))
