@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="largest_fragment",
                     choices=["small", "large_fragment", "precision_sweep", "largest_fragment", "serving",
-                             "copy_calibration", "mp2"])
+                             "copy_calibration", "mp2", "small_fragments"])
     ap.add_argument("--precisions", default="fp32,bf16x3,fp8",
                     help="comma list of candidate contraction precisions for the headline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--fock", action="store_true",
                     help="also time the headline precision with an f_ov block (non-canonical reference, "
                          "f_ia ~ N(0, 0.02^2), seeded), against its FP64 solve")
+    ap.add_argument("--sweep", action="store_true",
+                    help="precision sweep: every contraction precision on the whole solve, |dE_T| against the "
+                         "oracle's stored whole solve of the workload (tests/golden/<workload>_seed<seed>.json)")
     ap.add_argument("--formulation", default="occupied", choices=["occupied", "virtual"],
                     help="loop over unique occupied triples (default) or unique virtual triples")
     return ap.parse_args()
@@ -232,6 +235,125 @@ def run_serving(args):
     raise SystemExit(SERVING_DISABLED)
 
 
+def stored_oracle(workload, seed, x):
+    """The oracle's stored whole solve of a workload (E_T and per-triple
+    energies), if it exists and was computed from these inputs, else None."""
+    from synth import fingerprint
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_seed{seed}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    return rec if rec.get("input_fingerprint") == fingerprint(x) else None
+
+
+def run_sweep(args):
+    """Every contraction precision on the whole solve of one workload (FP64
+    denominators and compensated sums in all of them): seconds per solve,
+    TFLOP/s and |dE_T| against the oracle's stored whole solve."""
+    import torch
+
+    import paper_2502_17963_amd as bqc
+    from synth import CONFIGS, make_inputs
+    o, v, naux, seed = CONFIGS[args.workload]
+    x = make_inputs(o, v, naux, seed)
+    ref = stored_oracle(args.workload, seed, x)
+    dev = [torch.from_numpy(a).to("cuda:0") for a in x.arrays()]
+    torch.cuda.synchronize()
+    F = 12.0 * bqc.num_triples(o) * float(v) ** 3 * (v + o)
+    steps = args.steps if args.steps is not None else 2
+    recs = {}
+    for prec in ["fp64", "fp32", "bf16x3", "fp8"]:
+        for _ in range(max(args.warmup, 1)):
+            bqc.t_energy(o, v, *dev, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e = bqc.t_energy(o, v, *dev, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = {"E_T": e, "s": round(dt, 4), "tflops": round(F / dt / 1e12, 3),
+             "frac_of_peak": round(F / dt / 1e12 / PEAK_TFLOPS[prec], 4)}
+        if ref is not None:
+            r["dE_uEh_vs_oracle"] = abs(e - ref["E_T"]) * 1e6
+            r["rel_vs_oracle"] = abs(e - ref["E_T"]) / abs(ref["E_T"])
+        recs[prec] = r
+        print(f"[sweep] {prec}: E_T={e:.12e} {dt:.3f} s {r['tflops']} TFLOP/s "
+              f"dE={r.get('dE_uEh_vs_oracle', float('nan')):.3e} uEh", file=sys.stderr, flush=True)
+    out = {"metric": "precision sweep: (T) TFLOP/s and |dE_T| (uEh) vs the FP64 oracle per contraction precision",
+           "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True, "steps": steps, "warmup": args.warmup,
+           "data": "synthetic (seeded DF factors, MP1 t2, random t1)",
+           "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": naux, "seed": seed},
+           "oracle_E_T": ref["E_T"] if ref else None,
+           "oracle": ("stored whole solve of the FP64 oracle, tests/golden/" + f"{args.workload}_seed{seed}.json")
+           if ref else None,
+           "precisions": recs, "hip_runtime_version": bqc.runtime_versions()}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+def run_small_fragments(args):
+    """The serving stream's small fragments (nocc <= 12; about 40 of its 256)
+    solved one by one (bqc_t_energy_ex each) and as one batch
+    (bqc_t_energy_batch: grouped launches over all of them), split-BF16x3,
+    inputs generated on the GPU and resident: fragments per second both ways,
+    and every batched energy bitwise equal to its solve alone."""
+    import torch
+
+    import paper_2502_17963_amd as bqc
+    from synth import flops_alg, make_inputs_device, serving_stream
+    prec = "bf16x3"
+    shapes = [s for s in serving_stream(256) if s["nocc"] <= 12]
+    frags = []
+    for sh in shapes:
+        frags.append((sh["nocc"], sh["nvir"], *make_inputs_device(sh["nocc"], sh["nvir"], sh["naux"], sh["seed"])))
+    torch.cuda.synchronize()
+    F = sum(flops_alg(sh["nocc"], sh["nvir"]) for sh in shapes)
+    steps = args.steps if args.steps is not None else 3
+
+    def one_by_one():
+        return [bqc.t_energy(f[0], f[1], *f[2:], precision=prec) for f in frags]
+
+    def batched():
+        return bqc.t_energy_batch(frags, precision=prec)
+
+    res = {}
+    for name, fn in [("one_by_one", one_by_one), ("batch", batched)]:
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"s": round(dt, 5), "fragments_per_s": round(len(frags) / dt, 2),
+                     "tflops": round(F / dt / 1e12, 3), "energies": e}
+        print(f"[small fragments] {name}: {dt * 1e3:.2f} ms for {len(frags)} fragments, "
+              f"{len(frags) / dt:.1f} fragments/s, {F / dt / 1e12:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    same = res["batch"]["energies"] == res["one_by_one"]["energies"]
+    for r in res.values():
+        del r["energies"]
+    out = {"metric": "small fragments (nocc <= 12) per second, split-BF16x3, one by one vs batched",
+           "value": res["batch"]["fragments_per_s"], "unit": "fragments/s", "n_gpus": 1, "higher_is_better": True,
+           "steps": steps, "warmup": args.warmup, "dtype": "bf16x3",
+           "data": "synthetic fragments of the serving stream's shape distribution, generated on the GPU",
+           "config": {"workload": "small_fragments", "fragments": len(frags),
+                      "nocc": sorted(set(sh["nocc"] for sh in shapes)),
+                      "nvir_range": [min(sh["nvir"] for sh in shapes), max(sh["nvir"] for sh in shapes)],
+                      "flops": F},
+           "one_by_one": res["one_by_one"], "batch": res["batch"],
+           "speedup": round(res["one_by_one"]["s"] / res["batch"]["s"], 3), "batch_bitwise_equal_alone": same,
+           "hip_runtime_version": bqc.runtime_versions()}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
 MP2_SHAPES = [(32, 300, 1000), (48, 480, 1600), (100, 1000, 3000)]
 
 
@@ -307,6 +429,10 @@ def main():
         return run_copy_calibration(args)
     if args.workload == "mp2":
         return run_mp2(args)
+    if args.workload == "small_fragments":
+        return run_small_fragments(args)
+    if args.sweep:
+        return run_sweep(args)
     import numpy as np
     import torch
 

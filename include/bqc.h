@@ -190,6 +190,44 @@ int bqc_mp2_energy_df(int32_t nocc, int32_t nvir, int32_t naux,
                       const double* eps_o, const double* eps_v, const double* b_ov,
                       const bqc_t_opts* opts, double* E_MP2, bqc_t_stats* stats);
 
+/* ------------------------------------------------------------------ batch
+ * Several independent fragments solved together (the fragments of the
+ * paper's embedding layer, section 2.5, are independent (T) problems of
+ * uneven size).  Small fragments are bound by launch overhead when solved
+ * one by one (the batching argument of section 2.4.2); here each step of
+ * the path is one grouped launch over all fragments (operand conversion, then
+ * rounds of contraction / epilogue / per-triple sums over every fragment's
+ * current triple batch, then the totals).  E_T[f] is bitwise the energy
+ * bqc_t_energy_ex returns for fragment f alone with the same options.
+ *
+ * frags[f] holds fragment f's sizes and its seven inputs (layouts as for
+ * bqc_t_energy); opts (may be NULL) applies to all of them: precision,
+ * device, inputs_on_device (then every pointer of every fragment is a
+ * device pointer) and stream are used; formulation must be
+ * BQC_FORM_OCCUPIED and triple_begin / triple_end / fock_ov /
+ * triple_energies must be zero (else BQC_EINVAL); timing is ignored.  E_T
+ * is a HOST array of nfrag doubles, written only on BQC_OK.  nfrag = 0 is
+ * BQC_OK with nothing written.  An invalid fragment fails the whole call
+ * with BQC_EINVAL (the message names the fragment).  stats (may be NULL):
+ * the batch's gpu_s, total_s, upload_s, summed flops and triples,
+ * footprint_bytes (bqc_t_batch_footprint), gemm_launches (grouped
+ * contraction launches) and epilogue_launches (grouped epilogue launches).
+ * The H buffers of a batch take at most 8 GiB together (fragments then run
+ * their triples in more rounds); the rest of the workspace grows with the
+ * fragments' sizes.
+ */
+typedef struct {
+    int32_t nocc, nvir;
+    const double *eps_o, *eps_v, *t1, *t2, *ovvv, *ooov, *ovov;
+} bqc_t_fragment;
+
+int bqc_t_energy_batch(int32_t nfrag, const bqc_t_fragment* frags, const bqc_t_opts* opts,
+                       double* E_T, bqc_t_stats* stats);
+
+/* Device bytes a batch of these fragment shapes holds (inputs included, as
+ * for host inputs), or -1 for invalid arguments. */
+int64_t bqc_t_batch_footprint(int32_t nfrag, const int32_t* nocc, const int32_t* nvir, int32_t precision);
+
 /* Number of unique triples p <= q <= r (p = q = r excluded) of an orbital
  * space of n orbitals: the occupied triples for n = nocc, the virtual
  * triples of BQC_FORM_VIRTUAL for n = nvir (0 for n < 1). */

@@ -7,6 +7,7 @@ from .binding import (  # noqa: F401
     BqcError,
     Server,
     PRECISIONS,
+    batch_footprint,
     footprint,
     header_functions,
     last_error,
@@ -16,11 +17,12 @@ from .binding import (  # noqa: F401
     num_triples,
     runtime_versions,
     t_energy,
+    t_energy_batch,
     t_energy_df,
     t_energy_noalloc,
     t_energy_plain,
 )
 
-__all__ = ["BqcError", "Server", "PRECISIONS", "footprint", "header_functions", "last_error", "lib",
-           "mp2_energy_df", "noalloc_batch", "num_triples", "runtime_versions", "t_energy", "t_energy_df",
+__all__ = ["BqcError", "Server", "PRECISIONS", "batch_footprint", "footprint", "header_functions", "last_error", "lib",
+           "mp2_energy_df", "noalloc_batch", "num_triples", "runtime_versions", "t_energy", "t_energy_batch", "t_energy_df",
            "t_energy_noalloc", "t_energy_plain"]

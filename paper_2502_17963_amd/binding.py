@@ -51,6 +51,12 @@ class TStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Fragment(ctypes.Structure):
+    """bqc_t_fragment"""
+    _fields_ = [("nocc", ctypes.c_int32), ("nvir", ctypes.c_int32)] + \
+               [(name, _dp) for name in ("eps_o", "eps_v", "t1", "t2", "ovvv", "ooov", "ovov")]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
@@ -96,6 +102,12 @@ def lib():
             L.bqc_mp2_energy_df.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp,
                                             ctypes.POINTER(TOpts), _dp, ctypes.POINTER(TStats)]
             L.bqc_mp2_energy_df.restype = ctypes.c_int
+            L.bqc_t_energy_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Fragment), ctypes.POINTER(TOpts), _dp,
+                                             ctypes.POINTER(TStats)]
+            L.bqc_t_energy_batch.restype = ctypes.c_int
+            L.bqc_t_batch_footprint.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+            L.bqc_t_batch_footprint.restype = ctypes.c_int64
             L.bqc_t_num_triples.argtypes = [ctypes.c_int32]
             L.bqc_t_num_triples.restype = ctypes.c_int64
             L.bqc_t_footprint.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -341,6 +353,51 @@ def mp2_energy_df(nocc, nvir, naux, eps_o, eps_v, b_ov, device=0, stream=None, s
     if pair_energies:
         return e.value, {"pairs": pairs[:nocc * (nocc + 1) // 2], "stats": st.as_dict()}
     return (e.value, st.as_dict()) if stats else e.value
+
+
+def t_energy_batch(fragments, precision="fp64", device=0, stream=None, stats=False):
+    """E_T of several fragments through bqc_t_energy_batch.
+
+    fragments: sequence of (nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov),
+    all host numpy arrays or all device tensors.  Returns the list of energies,
+    or (energies, stats dict) with stats=True."""
+    n = len(fragments)
+    arr = (Fragment * max(n, 1))()
+    keep = []
+    on_dev = None
+    for f, fr in enumerate(fragments):
+        ptrs, dev, k = _ptrs(tuple(fr[2:9]))
+        if on_dev is None:
+            on_dev = dev
+        elif dev != on_dev:
+            raise ValueError("all fragments' inputs must live on the same side (host or device)")
+        keep.append(k)
+        arr[f].nocc, arr[f].nvir = int(fr[0]), int(fr[1])
+        for name, p in zip(("eps_o", "eps_v", "t1", "t2", "ovvv", "ooov", "ovov"), ptrs):
+            setattr(arr[f], name, p)
+    opts = TOpts()
+    opts.precision = _prec(precision)
+    opts.device = device
+    opts.inputs_on_device = 1 if on_dev else 0
+    if stream is not None:
+        opts.stream = ctypes.c_void_p(stream)
+    elif on_dev:
+        opts.stream = ctypes.c_void_p(_torch_stream(fragments[0][2]))
+    e = (ctypes.c_double * max(n, 1))()
+    st = TStats()
+    rc = lib().bqc_t_energy_batch(n, arr, ctypes.byref(opts), e, ctypes.byref(st))
+    del keep
+    _check(rc)
+    out = [e[f] for f in range(n)]
+    return (out, st.as_dict()) if stats else out
+
+
+def batch_footprint(shapes, precision="fp64") -> int:
+    """bqc_t_batch_footprint for [(nocc, nvir), ...] (-1 for invalid arguments)."""
+    n = len(shapes)
+    o = (ctypes.c_int32 * max(n, 1))(*[s[0] for s in shapes])
+    v = (ctypes.c_int32 * max(n, 1))(*[s[1] for s in shapes])
+    return int(lib().bqc_t_batch_footprint(n, o, v, _prec(precision)))
 
 
 def t_energy_plain(nocc, nvir, eps_o, eps_v, t1, t2, ovvv, ooov, ovov):

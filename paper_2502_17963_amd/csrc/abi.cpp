@@ -233,6 +233,116 @@ int solve_impl(int32_t o, int32_t v, const double* eps_o, const double* eps_v, c
     return BQC_OK;
 }
 
+// Several fragments in one batched solve (batch.hip).
+int batch_impl(int32_t nfrag, const bqc_t_fragment* frags, const bqc_t_opts* opts, double* E_T, bqc_t_stats* stats) {
+    bqc_t_opts op;
+    std::memset(&op, 0, sizeof(op));
+    if (opts) op = *opts;
+    if (nfrag < 0 || (nfrag > 0 && (!frags || !E_T))) return fail(BQC_EINVAL, "nfrag < 0, or null frags / E_T");
+    if (nfrag > (1 << 20)) return fail(BQC_EINVAL, "more fragments than one batch supports (2^20)");
+    if (op.precision < 0 || op.precision > 3) return fail(BQC_EINVAL, "unknown precision");
+    if (op.formulation != BQC_FORM_OCCUPIED)
+        return fail(BQC_EINVAL, "a batch runs the loop over occupied triples");
+    if (op.triple_begin != 0 || op.triple_end != 0 || op.fock_ov || op.triple_energies)
+        return fail(BQC_EINVAL, "a batch takes no triple range, f_ov block or per-triple output");
+    const bool dev_in = op.inputs_on_device != 0;
+    for (int32_t f = 0; f < nfrag; ++f) {
+        const bqc_t_fragment& x = frags[f];
+        const int rc = validate(x.nocc, x.nvir, x.eps_o, x.eps_v, x.t1, x.t2, x.ovvv, x.ooov, x.ovov, !dev_in);
+        if (rc != BQC_OK) return fail(rc, "fragment " + std::to_string(f) + ": " + g_last_error);
+    }
+    if (nfrag == 0) return BQC_OK;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BQC_EDEVICE, "no HIP device");
+    if (op.device < 0 || op.device >= ndev) return fail(BQC_EINVAL, "device ordinal out of range");
+    auto wall0 = std::chrono::steady_clock::now();
+    DeviceGuard dg(op.device);
+    Ctx* ctx = acquire_ctx(op.device);
+    struct Rel { Ctx* c; ~Rel() { release_ctx(c); } } rel{ctx};
+    if (!ctx->stream) BQC_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+    hipStream_t st = op.stream ? (hipStream_t)op.stream : ctx->stream;
+    std::vector<const double*> src((size_t)7 * nfrag);
+    for (int32_t f = 0; f < nfrag; ++f) {
+        const bqc_t_fragment& x = frags[f];
+        const double* a[7] = {x.eps_o, x.eps_v, x.t1, x.t2, x.ovvv, x.ooov, x.ovov};
+        for (int k = 0; k < 7; ++k) src[(size_t)7 * f + k] = a[k];
+    }
+    if (dev_in) {  // check the orbital energies from host copies
+        for (int32_t f = 0; f < nfrag; ++f) {
+            const bqc_t_fragment& x = frags[f];
+            std::vector<double> eo(x.nocc), ev(x.nvir);
+            BQC_HIP(hipMemcpyAsync(eo.data(), x.eps_o, x.nocc * sizeof(double), hipMemcpyDeviceToHost, st));
+            BQC_HIP(hipMemcpyAsync(ev.data(), x.eps_v, x.nvir * sizeof(double), hipMemcpyDeviceToHost, st));
+            BQC_HIP(hipStreamSynchronize(st));
+            const int rc = validate(x.nocc, x.nvir, eo.data(), ev.data(), x.t1, x.t2, x.ovvv, x.ooov, x.ovov, true);
+            if (rc != BQC_OK) return fail(rc, "fragment " + std::to_string(f) + ": " + g_last_error);
+        }
+    }
+    // inputs: device pointers as given, or uploaded into one buffer
+    std::vector<const double*> dst = src;
+    double upload_s = 0.0;
+    size_t in_bytes = 0;
+    if (!dev_in) {
+        for (int32_t f = 0; f < nfrag; ++f) in_bytes += a256((size_t)input_bytes(frags[f].nocc, frags[f].nvir));
+        ensure(ctx->in, ctx->in_size, in_bytes);
+        char* p = (char*)ctx->in;
+        const auto u0 = std::chrono::steady_clock::now();
+        for (int32_t f = 0; f < nfrag; ++f) {
+            const int o = frags[f].nocc, v = frags[f].nvir;
+            const size_t sizes[7] = {(size_t)o, (size_t)v, (size_t)o * v, (size_t)o * o * v * v,
+                                     (size_t)o * v * v * v, (size_t)o * o * o * v, (size_t)o * v * o * v};
+            char* q = p;
+            for (int k = 0; k < 7; ++k) {
+                BQC_HIP(hipMemcpyAsync(q, src[(size_t)7 * f + k], sizes[k] * sizeof(double), hipMemcpyHostToDevice,
+                                       st));
+                dst[(size_t)7 * f + k] = (const double*)q;
+                q += a256(sizes[k] * sizeof(double));
+            }
+            p += a256((size_t)input_bytes(o, v));
+        }
+        BQC_HIP(hipStreamSynchronize(st));
+        upload_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - u0).count();
+    }
+    std::vector<DevInputs> ins(nfrag);
+    std::vector<int> no(nfrag), nv(nfrag);
+    for (int32_t f = 0; f < nfrag; ++f) {
+        DevInputs& in = ins[f];
+        in.o = no[f] = frags[f].nocc;
+        in.v = nv[f] = frags[f].nvir;
+        in.eps_o = dst[(size_t)7 * f]; in.eps_v = dst[(size_t)7 * f + 1]; in.t1 = dst[(size_t)7 * f + 2];
+        in.t2 = dst[(size_t)7 * f + 3]; in.ovvv = dst[(size_t)7 * f + 4]; in.ooov = dst[(size_t)7 * f + 5];
+        in.ovov = dst[(size_t)7 * f + 6];
+    }
+    const BatchPlan bp = plan_batch(nfrag, no.data(), nv.data(), op.precision);
+    ensure(ctx->ws, ctx->ws_size, bp.total);
+    std::vector<double> e(nfrag);
+    SolveStats ss;
+    enqueue_batch(bp, op.precision, nfrag, ins.data(), ctx->ws, st, e.data(), stats ? &ss : nullptr);
+    for (int32_t f = 0; f < nfrag; ++f)
+        if (!std::isfinite(e[f])) return fail(BQC_EDEVICE, "non-finite energy of fragment " + std::to_string(f));
+    std::memcpy(E_T, e.data(), nfrag * sizeof(double));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        double flops = 0;
+        int64_t ntrip = 0;
+        for (int32_t f = 0; f < nfrag; ++f) {
+            const double v = frags[f].nvir;
+            flops += 12.0 * (double)num_triples(frags[f].nocc) * v * v * v * (v + frags[f].nocc);
+            ntrip += num_triples(frags[f].nocc);
+        }
+        stats->upload_s = upload_s;
+        stats->gpu_s = ss.gpu_s;
+        stats->flops = flops;
+        stats->footprint_bytes = bp.total + in_bytes;
+        stats->gemm_launches = ss.gemm_launches;
+        stats->epilogue_launches = ss.epi_launches;
+        stats->precision = op.precision;
+        stats->n_triples = (int32_t)std::min<int64_t>(ntrip, INT32_MAX);
+        stats->total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - wall0).count();
+    }
+    return BQC_OK;
+}
+
 // MP2 energy (density-fitted): validation, residency, one enqueue_mp2.
 int mp2_impl(int32_t o, int32_t v, int32_t naux, const double* eps_o, const double* eps_v, const double* b_ov,
              const bqc_t_opts* opts, double* E, bqc_t_stats* stats) {
@@ -377,6 +487,24 @@ int bqc_t_energy_df(int32_t nocc, int32_t nvir, int32_t naux, const double* eps_
 int bqc_mp2_energy_df(int32_t nocc, int32_t nvir, int32_t naux, const double* eps_o, const double* eps_v,
                       const double* b_ov, const bqc_t_opts* opts, double* E_MP2, bqc_t_stats* stats) {
     return guarded([&] { return mp2_impl(nocc, nvir, naux, eps_o, eps_v, b_ov, opts, E_MP2, stats); });
+}
+
+int bqc_t_energy_batch(int32_t nfrag, const bqc_t_fragment* frags, const bqc_t_opts* opts, double* E_T,
+                       bqc_t_stats* stats) {
+    return guarded([&] { return batch_impl(nfrag, frags, opts, E_T, stats); });
+}
+
+int64_t bqc_t_batch_footprint(int32_t nfrag, const int32_t* nocc, const int32_t* nvir, int32_t precision) {
+    if (nfrag < 0 || (nfrag > 0 && (!nocc || !nvir)) || precision < 0 || precision > 3) return -1;
+    std::vector<int> o(nfrag), v(nfrag);
+    int64_t in = 0;
+    for (int32_t f = 0; f < nfrag; ++f) {
+        if (nocc[f] < 1 || nvir[f] < 1) return -1;
+        o[f] = nocc[f];
+        v[f] = nvir[f];
+        in += (int64_t)a256((size_t)input_bytes(o[f], v[f]));
+    }
+    return (int64_t)plan_batch(nfrag, o.data(), v.data(), precision).total + in;
 }
 
 int64_t bqc_t_num_triples(int32_t nocc) { return num_triples(nocc); }

@@ -122,6 +122,16 @@ struct GemmLaunch {
                            // (n = v, or o for FORM_VIR)
 };
 
+// Grouped launches: one launch covers the current triple batch of several
+// solves (fragments).  Each entry describes one fragment's part and the first
+// logical work group (or block) of that part; entries are in increasing
+// order of it, and a work group finds its entry by binary search.
+struct GemmGroupEntry {
+    GemmLaunch g;
+    int nblk, ntile_u, ntile_w;  // the fragment's tiling (contraction_tiling)
+    int wg0;                     // first logical work group of this entry
+};
+
 // The epilogue is written for triples (i, j, k) of one orbital space and
 // tiles of the other: o is the size of the triples' space and v that of the
 // tiles' space, eps_o / eps_v their orbital energies, t1 [o][v], ovov
@@ -205,6 +215,22 @@ struct KernelCall {
 void launch_prepare(int precision, const DevInputs& in, void* ws_ops, Operands* ops,
                     hipStream_t st, int form = FORM_OCC);
 
+// The operand conversion of several solves (loop over occupied triples,
+// (ia|bc) given) in one launch per factor: entry x converts its factor
+// (`src` -> `dst`, nmat matrices of `rows` rows, contraction length len
+// padded to kpad) with blocks [b0, b0 + nb).  ws[f] is solve f's operand
+// area (prepare_bytes); `tables` (host) and d_tables (device, 4 n entries)
+// must stay valid until the stream has passed the launches.
+struct FactorGroupEntry {
+    const double* src;
+    void* dst;
+    int64_t nmat;
+    int rows, len, kpad, o, v;
+    int b0, nb;
+};
+void launch_prepare_group(int precision, int n, const DevInputs* ins, void* const* ws, Operands* ops,
+                          FactorGroupEntry* d_tables, std::vector<FactorGroupEntry>& tables, hipStream_t st);
+
 // Transposed FP64 inputs of the virtual-triple loop's epilogue (see
 // EpiLaunch), built once per solve: -eps_v, -eps_o, t1[a][i], (ia|jb) as
 // ovov_t[a][b][i][j] (an o x o matrix per virtual pair, so that the
@@ -229,6 +255,37 @@ KernelCall gemm_call(int precision, const GemmLaunch& g, int form = FORM_OCC);
 // tiles of min_wb .. 5 blocks are considered.
 int wave_blocks(int n, int min_wb = 2);
 KernelCall epilogue_call(int precision, const EpiLaunch& e);
+
+// Tiling of one contraction launch with wave tiles of wb x wb blocks:
+// 16-blocks of the tile space, tiles along rows and columns, and the work
+// groups of a launch of ntrip triples (3 pairs x n planes x tiles).
+struct Tiling {
+    int nblk, ntile_u, ntile_w;
+    int64_t n_wg;
+};
+Tiling contraction_tiling(int n, int wb, int ntrip);
+struct EpiGroupEntry {
+    EpiLaunch e;
+    int wg0;  // first logical work group: ntrip x norbit groups per entry
+};
+struct RedGroupEntry {
+    const double* partial;  // [ntrip][norbit]
+    int norbit;
+    const int4* trip;
+    double* e_trip;         // per-triple energies of the entry's triples
+    int b0;                 // first block: one block per triple
+};
+struct TotalGroupEntry {
+    const double* e_trip;
+    int64_t n;
+    double* out;
+};
+// Grouped contraction (loop over occupied triples, wave tile wb x wb for
+// every entry), epilogue, per-triple sums and totals (one block per entry).
+KernelCall gemm_group_call(int precision, int wb, const GemmGroupEntry* d_ent, int nent, int64_t n_wg);
+KernelCall epilogue_group_call(int precision, const EpiGroupEntry* d_ent, int nent, int64_t n_wg);
+KernelCall reduce_triples_group_call(const RedGroupEntry* d_ent, int nent, int nblocks);
+KernelCall reduce_total_group_call(const TotalGroupEntry* d_ent, int nent);
 KernelCall reduce_triples_call(const double* partial, int ntrip, int norbit, const int4* trip,
                                double* e_trip);
 KernelCall reduce_total_call(const double* e_trip, int64_t n, double* out);
@@ -283,5 +340,31 @@ double* workspace_energy(void* ws, int o, int v, int precision, int form = FORM_
 
 void enqueue_solve(const Plan& plan, const DevInputs& in, void* ws, double* d_energy,
                    hipStream_t st, hipStream_t side, bool timing, SolveStats* stats, bool graph = false);
+
+// ------------------------------------------------------------------ batch
+// Several fragments solved together with grouped launches (batch.hip), loop
+// over occupied triples.  Workspace offsets (bytes) of one fragment's parts.
+struct BatchFrag {
+    int o = 0, v = 0;
+    int64_t ntrip = 0;
+    int norbit = 0;
+    int nb = 0;                              // triples per round
+    size_t ops = 0, hbuf = 0, partial = 0, etrip = 0;
+    size_t trip = 0, orbits = 0;             // offsets inside the tables region
+};
+struct BatchPlan {
+    int rounds = 0;
+    std::vector<BatchFrag> frag;
+    size_t tabs = 0, tabs_bytes = 0;         // triple and orbit tables of all fragments
+    size_t factor_tab = 0;                   // operand-conversion entries
+    size_t entries = 0, entries_bytes = 0;   // grouped-launch entries of every round
+    size_t energies = 0;                     // the fragments' energies, contiguous
+    size_t total = 0;                        // workspace bytes
+};
+BatchPlan plan_batch(int n, const int* nocc, const int* nvir, int precision);
+// Enqueues the whole batch on st (inputs device resident), copies the n
+// energies to energies_host and returns after st has drained.
+void enqueue_batch(const BatchPlan& bp, int precision, int n, const DevInputs* ins, void* ws, hipStream_t st,
+                   double* energies_host, SolveStats* stats);
 
 }  // namespace bqc

@@ -55,9 +55,9 @@ __device__ __forceinline__ double keep_if(double x, bool keep) {
 // f_ia t_jk^bc + f_jb t_ik^ac + f_kc t_ij^ab (paper Eqs. 5 and 7), staged
 // exactly like the singles term (t2 blocks in place of (ov|ov) blocks, f_ov
 // slices in place of t1 slices).
+// Tile orbit `orb` of triple `t` of the launch e.
 template <typename HT, bool FOCK>
-__global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
-    const int orb = blockIdx.x, t = blockIdx.y;
+__device__ __forceinline__ void epilogue_body(const EpiLaunch& e, int orb, int t) {
     const int4 ob = e.orbits[orb];
     const int4 tr = e.trip[t];
     const int i = tr.x, j = tr.y, k = tr.z;
@@ -222,6 +222,33 @@ __global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
     }
 }
 
+template <typename HT, bool FOCK>
+__global__ __launch_bounds__(E_THREADS) void epilogue_kernel(EpiLaunch e) {
+    epilogue_body<HT, FOCK>(e, blockIdx.x, blockIdx.y);
+}
+
+// Index of the entry with the largest first block <= b (entries ascending).
+template <typename T>
+__device__ __forceinline__ int group_entry(const T* __restrict__ ent, int nent, int b) {
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].wg0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One epilogue launch over several solves: entry e has ntrip x norbit work
+// groups from its wg0 on (orbit fastest).
+template <typename HT>
+__global__ __launch_bounds__(E_THREADS) void epilogue_group_kernel(const EpiGroupEntry* __restrict__ ent, int nent) {
+    const int b = blockIdx.x;
+    const EpiGroupEntry x = ent[group_entry(ent, nent, b)];
+    const int l = b - x.wg0;
+    epilogue_body<HT, false>(x.e, l % x.e.norbit, l / x.e.norbit);
+}
+
 // Neumaier compensated accumulation: (s, c) += x
 __device__ __forceinline__ void neu_add(double& s, double& c, double x) {
     const double t = s + x;
@@ -279,6 +306,29 @@ __global__ __launch_bounds__(R_THREADS) void reduce_total_kernel(const double* e
     if (threadIdx.x == 0) *out = s;
 }
 
+// Per-triple sums of several solves: one block per triple, entry by entry.
+__global__ __launch_bounds__(R_THREADS) void reduce_triples_group_kernel(const RedGroupEntry* __restrict__ ent,
+                                                                           int nent) {
+    int lo = 0, hi = nent - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const RedGroupEntry x = ent[lo];
+    const int t = b - x.b0;
+    const double s = block_sum_fixed(x.partial + (int64_t)t * x.norbit, x.norbit);
+    if (threadIdx.x == 0) x.e_trip[t] = s * (double)x.trip[t].w / 3.0;
+}
+
+// The totals of several solves: one block per entry.
+__global__ __launch_bounds__(R_THREADS) void reduce_total_group_kernel(const TotalGroupEntry* __restrict__ ent) {
+    const TotalGroupEntry x = ent[blockIdx.x];
+    const double s = block_sum_fixed(x.e_trip, x.n);
+    if (threadIdx.x == 0) *x.out = s;
+}
+
 }  // namespace
 
 KernelCall epilogue_call(int precision, const EpiLaunch& e) {
@@ -290,6 +340,34 @@ KernelCall epilogue_call(int precision, const EpiLaunch& e) {
     k.grid = dim3(e.norbit, e.ntrip);
     k.block = dim3(E_THREADS);
     k.arg(e);
+    return k;
+}
+
+KernelCall epilogue_group_call(int precision, const EpiGroupEntry* d_ent, int nent, int64_t n_wg) {
+    if (n_wg > ((int64_t)1 << 31) - 1) throw Error(-1, "grouped epilogue grid too large");
+    KernelCall k;
+    k.fn = precision == 0 ? (const void*)&epilogue_group_kernel<double> : (const void*)&epilogue_group_kernel<float>;
+    k.grid = dim3((unsigned)n_wg);
+    k.block = dim3(E_THREADS);
+    k.arg(d_ent).arg(nent);
+    return k;
+}
+
+KernelCall reduce_triples_group_call(const RedGroupEntry* d_ent, int nent, int nblocks) {
+    KernelCall k;
+    k.fn = (const void*)&reduce_triples_group_kernel;
+    k.grid = dim3(nblocks);
+    k.block = dim3(R_THREADS);
+    k.arg(d_ent).arg(nent);
+    return k;
+}
+
+KernelCall reduce_total_group_call(const TotalGroupEntry* d_ent, int nent) {
+    KernelCall k;
+    k.fn = (const void*)&reduce_total_group_kernel;
+    k.grid = dim3(nent);
+    k.block = dim3(R_THREADS);
+    k.arg(d_ent);
     return k;
 }
 

@@ -290,20 +290,16 @@ __device__ __forceinline__ void stage_products(typename Mode<PREC>::Acc (&acc)[W
     }
 }
 
+// The work of logical work group L of one contraction launch of g (the
+// launch's tiles are nblk 16-blocks split into ntile_u x ntile_w tiles).
 template <int PREC, class G, int FORM>
-__global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile_u,
-                                                              int ntile_w, int per_xcd) {
+__device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk, int ntile_u, int ntile_w) {
     constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, NVEC = G::NVEC, WB = G::WB;
     typedef Mode<PREC> M;
     typedef typename M::Acc Acc;
     typedef typename M::HT HT;
     constexpr int KC = M::KC;
 
-    // XCD-aware order: hardware block hw runs on XCD hw % 8; each XCD gets a
-    // contiguous range of logical tiles (neighbours share operands in L2).
-    const int hw = blockIdx.x;
-    const int L = (hw % 8) * per_xcd + hw / 8;
-    if (L >= n_wg) return;
     const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
     // size of the space the planes, rows and columns of H run over
     const int n = FORM == FORM_VIR ? o : v;
@@ -456,6 +452,37 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
                     if (u < n && w < n) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
                 }
             }
+}
+
+template <int PREC, class G, int FORM>
+__global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_wg, int nblk, int ntile_u,
+                                                              int ntile_w, int per_xcd) {
+    // XCD-aware order: hardware block hw runs on XCD hw % 8; each XCD gets a
+    // contiguous range of logical tiles (neighbours share operands in L2).
+    const int hw = blockIdx.x;
+    const int L = (hw % 8) * per_xcd + hw / 8;
+    if (L >= n_wg) return;
+    h_gemm_body<PREC, G, FORM>(g, L, nblk, ntile_u, ntile_w);
+}
+
+// One contraction launch over several solves (fragments) at once: entry e
+// holds a launch of one fragment, its tiling and the first logical work
+// group of the launch (entries in increasing order of wg0); logical work
+// group L runs work group L - wg0 of the entry with the largest wg0 <= L.
+template <int PREC, class G>
+__global__ __launch_bounds__(G::NTHR, 1) void h_gemm_group_kernel(const GemmGroupEntry* __restrict__ ent, int nent,
+                                                                    int n_wg, int per_xcd) {
+    const int hw = blockIdx.x;
+    const int L = (hw % 8) * per_xcd + hw / 8;
+    if (L >= n_wg) return;
+    int lo = 0, hi = nent - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].wg0 <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    const GemmGroupEntry e = ent[lo];
+    h_gemm_body<PREC, G, FORM_OCC>(e.g, L - e.wg0, e.nblk, e.ntile_u, e.ntile_w);
 }
 
 // The loop over virtual triples has small planes (n = nocc rows and
@@ -688,6 +715,40 @@ int wave_blocks(int n, int min_wb) {
         if (u > 1.2 * use) { use = u; best = wb; }
     }
     return best;
+}
+
+namespace {
+template <int PREC, int WB>
+KernelCall group_call_wb(const GemmGroupEntry* d_ent, int nent, int64_t n_wg) {
+    if (n_wg > ((int64_t)1 << 31) - 8) throw Error(-1, "grouped contraction grid too large");
+    const int per_xcd = ceil_div((int)n_wg, 8);
+    KernelCall k;
+    k.fn = (const void*)&h_gemm_group_kernel<PREC, Geo<2, 2, WB>>;
+    k.grid = dim3(per_xcd * 8);
+    k.block = dim3(Geo<2, 2, WB>::NTHR);
+    k.arg(d_ent).arg(nent).arg((int)n_wg).arg(per_xcd);
+    return k;
+}
+template <int PREC>
+KernelCall group_call_prec(int wb, const GemmGroupEntry* d_ent, int nent, int64_t n_wg) {
+    switch (wb) {
+        case 2: return group_call_wb<PREC, 2>(d_ent, nent, n_wg);
+        case 3: return group_call_wb<PREC, 3>(d_ent, nent, n_wg);
+        case 4: return group_call_wb<PREC, 4>(d_ent, nent, n_wg);
+        case 5: return group_call_wb<PREC, 5>(d_ent, nent, n_wg);
+        default: throw Error(-1, "unsupported wave tile");
+    }
+}
+}  // namespace
+
+KernelCall gemm_group_call(int precision, int wb, const GemmGroupEntry* d_ent, int nent, int64_t n_wg) {
+    switch (precision) {
+        case 0: return group_call_prec<0>(wb, d_ent, nent, n_wg);
+        case 1: return group_call_prec<1>(wb, d_ent, nent, n_wg);
+        case 2: return group_call_prec<2>(wb, d_ent, nent, n_wg);
+        case 3: return group_call_prec<3>(wb, d_ent, nent, n_wg);
+        default: throw Error(-1, "unsupported precision for the MFMA contraction");
+    }
 }
 
 // Work groups of 2 x 2 waves; the wave tile is chosen per v (wave_blocks).

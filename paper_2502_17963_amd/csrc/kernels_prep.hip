@@ -88,13 +88,10 @@ constexpr bool vir_factor() { return F >= F_V_OVVV; }
 // [row0, row0 + nrows) of every matrix (matrices of `rows` rows); the
 // source is read at the row relative to row0.
 template <int PREC, int F>
-__global__ void make_factor(const double* __restrict__ src, void* dst, int64_t nmat, int rows, int row0,
-                            int nrows, int len, int kpad, int o, int v) {
+__device__ __forceinline__ void factor_elem(const double* __restrict__ src, void* dst, int64_t idx, int rows,
+                                            int row0, int nrows, int nchunk, int len, int o, int v) {
     constexpr int KC = (PREC == 0) ? 16 : 32;
-    const int nchunk = kpad / KC;
-    const int64_t n = nmat * nchunk * (int64_t)nrows * KC;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+    {
         const int kk = (int)(idx % KC);
         int64_t rest = idx / KC;
         const int64_t r = rest % nrows; rest /= nrows;
@@ -115,6 +112,36 @@ __global__ void make_factor(const double* __restrict__ src, void* dst, int64_t n
             d[32 + kk] = bf16_bits((float)(x - (double)bf16_value(h)));
         }
     }
+}
+
+template <int PREC, int F>
+__global__ void make_factor(const double* __restrict__ src, void* dst, int64_t nmat, int rows, int row0,
+                            int nrows, int len, int kpad, int o, int v) {
+    constexpr int KC = (PREC == 0) ? 16 : 32;
+    const int nchunk = kpad / KC;
+    const int64_t n = nmat * nchunk * (int64_t)nrows * KC;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        factor_elem<PREC, F>(src, dst, idx, rows, row0, nrows, nchunk, len, o, v);
+}
+
+// One factor of several solves in one launch: entry x covers blocks
+// [x.b0, x.b0 + x.nb) and converts all rows of all its matrices.
+template <int PREC, int F>
+__global__ void make_factor_group(const FactorGroupEntry* __restrict__ ent, int nent) {
+    constexpr int KC = (PREC == 0) ? 16 : 32;
+    int lo = 0, hi = nent - 1;
+    const int b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const FactorGroupEntry x = ent[lo];
+    const int nchunk = x.kpad / KC;
+    const int64_t n = x.nmat * nchunk * (int64_t)x.rows * KC;
+    for (int64_t idx = (int64_t)(b - x.b0) * blockDim.x + threadIdx.x; idx < n; idx += (int64_t)x.nb * blockDim.x)
+        factor_elem<PREC, F>(x.src, x.dst, idx, x.rows, 0, x.rows, nchunk, x.len, x.o, x.v);
 }
 
 // OCP FP8 e4m3 (bias 7, max 448, no infinities) of y with round-to-nearest-
@@ -377,6 +404,46 @@ void prepare_fp8(const DevInputs& in, void* ws, Operands* ops, hipStream_t st) {
 
 }  // namespace
 
+template <int PREC>
+void prepare_group_t(int n, const DevInputs* ins, void* const* ws, Operands* ops, FactorGroupEntry* d_tables,
+                     std::vector<FactorGroupEntry>& tables, hipStream_t st) {
+    tables.assign((size_t)4 * n, FactorGroupEntry{});
+    const int eb = operand_bytes(PREC);
+    int nblocks[4] = {0, 0, 0, 0};
+    for (int f = 0; f < n; ++f) {
+        const DevInputs& in = ins[f];
+        const int o = in.o, v = in.v;
+        const Sizes z = factor_sizes(o, v, PREC);
+        char* p = (char*)ws[f];
+        void* dst[4];
+        dst[0] = p; p += align256((size_t)z.m_ovvv * v * z.Kv * eb);
+        dst[1] = p; p += align256((size_t)z.m_t2 * v * z.Kv * eb);
+        dst[2] = p; p += align256((size_t)z.m_t2l * v * z.Ko * eb);
+        dst[3] = p;
+        const double* src[4] = {in.ovvv, in.t2, in.t2, in.ooov};
+        const int64_t nmat[4] = {z.m_ovvv, z.m_t2, z.m_t2l, z.m_hoo};
+        const int len[4] = {v, v, o, o}, kpad[4] = {z.Kv, z.Kv, z.Ko, z.Ko};
+        for (int k = 0; k < 4; ++k) {
+            FactorGroupEntry& x = tables[(size_t)k * n + f];
+            x.src = src[k]; x.dst = dst[k]; x.nmat = nmat[k]; x.rows = v; x.len = len[k]; x.kpad = kpad[k];
+            x.o = o; x.v = v;
+            const int64_t elems = nmat[k] * (int64_t)v * kpad[k];
+            x.nb = (int)std::max<int64_t>(1, std::min<int64_t>((elems + P_THREADS - 1) / P_THREADS, 4096));
+            x.b0 = nblocks[k];
+            nblocks[k] += x.nb;
+        }
+        ops[f].ovvv = dst[0]; ops[f].t2 = dst[1]; ops[f].t2l = dst[2]; ops[f].hoo = dst[3];
+        ops[f].Kv = z.Kv; ops[f].Ko = z.Ko;
+    }
+    BQC_HIP(hipMemcpyAsync(d_tables, tables.data(), tables.size() * sizeof(FactorGroupEntry), hipMemcpyHostToDevice,
+                           st));
+    hipLaunchKernelGGL((make_factor_group<PREC, F_OVVV>), dim3(nblocks[0]), dim3(P_THREADS), 0, st, d_tables, n);
+    hipLaunchKernelGGL((make_factor_group<PREC, F_T2>), dim3(nblocks[1]), dim3(P_THREADS), 0, st, d_tables + n, n);
+    hipLaunchKernelGGL((make_factor_group<PREC, F_T2L>), dim3(nblocks[2]), dim3(P_THREADS), 0, st, d_tables + 2 * n, n);
+    hipLaunchKernelGGL((make_factor_group<PREC, F_HOO>), dim3(nblocks[3]), dim3(P_THREADS), 0, st, d_tables + 3 * n, n);
+    BQC_HIP(hipGetLastError());
+}
+
 void launch_prepare(int precision, const DevInputs& in, void* ws, Operands* ops, hipStream_t st, int form) {
     if (form == FORM_VIR) {
         switch (precision) {
@@ -451,6 +518,18 @@ VirAux launch_vir_aux(const DevInputs& in, void* aux, hipStream_t st) {
         launch_aux(in.fock_ov, x.fock_t, ov, 0, o, v, st);
     }
     return x;
+}
+
+void launch_prepare_group(int precision, int n, const DevInputs* ins, void* const* ws, Operands* ops,
+                          FactorGroupEntry* d_tables, std::vector<FactorGroupEntry>& tables, hipStream_t st) {
+    switch (precision) {
+        case 0: prepare_group_t<0>(n, ins, ws, ops, d_tables, tables, st); return;
+        case 1: prepare_group_t<1>(n, ins, ws, ops, d_tables, tables, st); return;
+        case 2: prepare_group_t<2>(n, ins, ws, ops, d_tables, tables, st); return;
+        default:  // FP8 factors have their own converter: one launch set per solve
+            for (int f = 0; f < n; ++f) launch_prepare(precision, ins[f], ws[f], &ops[f], st);
+            return;
+    }
 }
 
 }  // namespace bqc

@@ -1,8 +1,9 @@
 // Host-side sizes of a solve's device buffers: operand element sizes and
-// paddings, the contraction operands' bytes, the density-fitting scratch and
-// the transposes of the loop over virtual triples.  Host code only (no
-// kernels), so the layout arithmetic is shared by the library and by the
-// host-side tests that run the solve driver against a stand-in runtime.
+// paddings, the contraction operands' bytes, the density-fitting scratch,
+// the transposes of the loop over virtual triples and the contraction's
+// tiling.  Host code only (no kernels), so the layout arithmetic is shared
+// by the library and by the host-side tests that run the solve driver
+// against a stand-in runtime.
 #include <algorithm>
 
 #include "bqc_internal.h"
@@ -58,6 +59,15 @@ int64_t prepare_bytes(int precision, int o, int v) {
              align256((size_t)z.m_t2l * v * z.Ko / 32) + align256((size_t)z.m_hoo * v * z.Ko / 32);
     }
     return b;
+}
+
+Tiling contraction_tiling(int n, int wb, int ntrip) {
+    Tiling t;
+    t.nblk = ceil_div(n, 16);
+    t.ntile_u = ceil_div(t.nblk, 2 * wb);
+    t.ntile_w = ceil_div(t.nblk, 2 * wb);
+    t.n_wg = (int64_t)ntrip * 3 * n * t.ntile_u * t.ntile_w;
+    return t;
 }
 
 int64_t vir_aux_bytes(int o, int v, bool fock) {

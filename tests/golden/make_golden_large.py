@@ -1,4 +1,4 @@
-"""Write the FP64 oracle's whole solve of the large fragment.
+"""Write the FP64 oracle's whole solve of a workload too large for a test.
 
 Calls only the FP64 oracle (``oracle.closed_shell.triple_energy``, one call
 per unique occupied triple, exactly as ``oracle.t_energy`` makes them) and
@@ -6,12 +6,14 @@ the seeded input generator.  The triples are spread over worker processes
 (each with one BLAS thread); the per-triple energies are collected in
 unique-triple order and summed with math.fsum, as ``oracle.t_energy`` does.
 
-Workload: nocc = 32, nvir = 300, naux = 1000, seed 0 (5952 unique triples,
-6.4e14 flops; one to two hours on eight host cores).  Output:
-tests/golden/large_fragment_seed0.json with E_T, every per-triple energy and
-a fingerprint of the generated inputs.  Run from the repository root:
+Workloads: large_fragment, nocc = 32, nvir = 300, naux = 1000, seed 0
+(5952 unique triples, 6.4e14 flops; about two hours on eight host cores),
+and precision_sweep, nocc = 24, nvir = 240, naux = 800, seed 0 (2576
+triples, 1.1e14 flops).  Output: tests/golden/<workload>_seed0.json with
+E_T, every per-triple energy and a fingerprint of the generated inputs.
+Run from the repository root:
 
-    python tests/golden/make_golden_large.py [--workers N]
+    python tests/golden/make_golden_large.py [--workload NAME] [--workers N]
 """
 import argparse
 import json
@@ -32,8 +34,8 @@ import multiprocessing as mp  # noqa: E402
 from oracle.closed_shell import triple_energy, triple_table  # noqa: E402
 from synth import fingerprint, make_inputs  # noqa: E402
 
-SHAPE = (32, 300, 1000, 0)
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "large_fragment_seed0.json")
+SHAPES = {"large_fragment": (32, 300, 1000, 0), "precision_sweep": (24, 240, 800, 0)}
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 _X = None  # inputs, inherited by the forked workers
 
@@ -47,8 +49,10 @@ def main():
     global _X
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=max(1, (os.cpu_count() or 2) - 2))
+    ap.add_argument("--workload", default="large_fragment", choices=sorted(SHAPES))
     a = ap.parse_args()
-    o, v, naux, seed = SHAPE
+    o, v, naux, seed = SHAPES[a.workload]
+    out_path = os.path.join(HERE, f"{a.workload}_seed{seed}.json")
     t0 = time.time()
     _X = make_inputs(o, v, naux, seed)
     table = triple_table(o)
@@ -68,10 +72,10 @@ def main():
     rec = {"nocc": o, "nvir": v, "naux": naux, "seed": seed, "generator": "synth.make_inputs",
            "oracle": "oracle.closed_shell.triple_energy per unique triple, math.fsum over triples",
            "input_fingerprint": fingerprint(_X), "E_T": e_t, "triples": terms}
-    with open(OUT, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(rec, f)
         f.write("\n")
-    print(f"E_T = {e_t!r}; wrote {OUT} after {time.time() - t0:.0f} s", flush=True)
+    print(f"E_T = {e_t!r}; wrote {out_path} after {time.time() - t0:.0f} s", flush=True)
 
 
 if __name__ == "__main__":

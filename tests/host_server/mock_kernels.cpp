@@ -28,6 +28,7 @@ namespace {
 inline size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 char k_gemm, k_epi, k_red_trip, k_red_total;  // addresses that stand for the kernels
+char k_gemm_group, k_epi_group, k_red_trip_group, k_red_total_group;
 
 float sig(int4 t, int h) { return (float)(h * 1000000 + t.x * 10000 + t.y * 100 + t.z); }
 
@@ -127,8 +128,72 @@ void emu_red_total(void** a) {
     *out = s;
 }
 
+// Grouped launches: each entry is emulated as the single launch it stands for.
+void emu_gemm_group(void** a) {
+    const GemmGroupEntry* ent = *(const GemmGroupEntry* const*)a[0];
+    const int nent = *(const int*)a[1], prec = *(const int*)a[2];
+    mock::check_range(ent, (size_t)nent * sizeof(GemmGroupEntry), "grouped contraction entries", false);
+    int64_t wg = 0;
+    for (int e = 0; e < nent; ++e) {
+        if (ent[e].wg0 != wg) {
+            std::fprintf(stderr, "MOCK-HIP FAULT: grouped contraction entry %d starts at %d, not %lld\n", e,
+                         ent[e].wg0, (long long)wg);
+            std::abort();
+        }
+        wg += (int64_t)ent[e].g.ntrip * 3 * ent[e].g.v * ent[e].ntile_u * ent[e].ntile_w;
+        GemmLaunch g = ent[e].g;
+        int form = FORM_OCC;
+        void* args[3] = {&g, (void*)&prec, &form};
+        emu_gemm(args);
+    }
+}
+
+void emu_epi_group(void** a) {
+    const EpiGroupEntry* ent = *(const EpiGroupEntry* const*)a[0];
+    const int nent = *(const int*)a[1], prec = *(const int*)a[2];
+    mock::check_range(ent, (size_t)nent * sizeof(EpiGroupEntry), "grouped epilogue entries", false);
+    for (int e = 0; e < nent; ++e) {
+        EpiLaunch x = ent[e].e;
+        int p = prec;
+        void* args[2] = {&x, &p};
+        emu_epi(args);
+    }
+}
+
+void emu_red_trip_group(void** a) {
+    const RedGroupEntry* ent = *(const RedGroupEntry* const*)a[0];
+    const int nent = *(const int*)a[1];
+    mock::check_range(ent, (size_t)nent * sizeof(RedGroupEntry), "grouped per-triple sum entries", false);
+    for (int e = 0; e < nent; ++e) {
+        const int ntrip = (e + 1 < nent ? ent[e + 1].b0 : *(const int*)a[2]) - ent[e].b0;
+        const double* partial = ent[e].partial;
+        int nt = ntrip, nb = ent[e].norbit;
+        const int4* trip = ent[e].trip;
+        double* out = ent[e].e_trip;
+        void* args[5] = {&partial, &nt, &nb, &trip, &out};
+        emu_red_trip(args);
+    }
+}
+
+void emu_red_total_group(void** a) {
+    const TotalGroupEntry* ent = *(const TotalGroupEntry* const*)a[0];
+    const int nent = *(const int*)a[1];
+    mock::check_range(ent, (size_t)nent * sizeof(TotalGroupEntry), "grouped total entries", false);
+    for (int e = 0; e < nent; ++e) {
+        const double* x = ent[e].e_trip;
+        int64_t n = ent[e].n;
+        double* out = ent[e].out;
+        void* args[3] = {&x, &n, &out};
+        emu_red_total(args);
+    }
+}
+
 struct Registrar {
     Registrar() {
+        mock::register_kernel(&k_gemm_group, {sizeof(void*), sizeof(int), sizeof(int)}, emu_gemm_group);
+        mock::register_kernel(&k_epi_group, {sizeof(void*), sizeof(int), sizeof(int)}, emu_epi_group);
+        mock::register_kernel(&k_red_trip_group, {sizeof(void*), sizeof(int), sizeof(int)}, emu_red_trip_group);
+        mock::register_kernel(&k_red_total_group, {sizeof(void*), sizeof(int)}, emu_red_total_group);
         mock::register_kernel(&k_gemm, {sizeof(GemmLaunch), sizeof(int), sizeof(int)}, emu_gemm);
         mock::register_kernel(&k_epi, {sizeof(EpiLaunch), sizeof(int)}, emu_epi);
         mock::register_kernel(&k_red_trip, {sizeof(void*), sizeof(int), sizeof(int), sizeof(void*), sizeof(void*)},
@@ -214,6 +279,44 @@ KernelCall reduce_total_call(const double* e_trip, int64_t n, double* out) {
 }
 
 int wave_blocks(int, int) { return 5; }
+
+void launch_prepare_group(int precision, int n, const DevInputs* ins, void* const* ws, Operands* ops,
+                          FactorGroupEntry* d_tables, std::vector<FactorGroupEntry>& tables, hipStream_t st) {
+    tables.assign((size_t)4 * n, FactorGroupEntry{});
+    for (int f = 0; f < n; ++f) launch_prepare(precision, ins[f], ws[f], &ops[f], st, FORM_OCC);
+    mock::submit(st, [=] { mock::check_range(d_tables, (size_t)4 * n * sizeof(FactorGroupEntry), "factor tables", true); });
+}
+
+KernelCall gemm_group_call(int precision, int wb, const GemmGroupEntry* d_ent, int nent, int64_t n_wg) {
+    (void)wb;
+    (void)n_wg;
+    KernelCall k;
+    k.fn = &k_gemm_group;
+    k.arg(d_ent).arg(nent).arg(precision);
+    return k;
+}
+
+KernelCall epilogue_group_call(int precision, const EpiGroupEntry* d_ent, int nent, int64_t n_wg) {
+    (void)n_wg;
+    KernelCall k;
+    k.fn = &k_epi_group;
+    k.arg(d_ent).arg(nent).arg(precision);
+    return k;
+}
+
+KernelCall reduce_triples_group_call(const RedGroupEntry* d_ent, int nent, int nblocks) {
+    KernelCall k;
+    k.fn = &k_red_trip_group;
+    k.arg(d_ent).arg(nent).arg(nblocks);
+    return k;
+}
+
+KernelCall reduce_total_group_call(const TotalGroupEntry* d_ent, int nent) {
+    KernelCall k;
+    k.fn = &k_red_total_group;
+    k.arg(d_ent).arg(nent);
+    return k;
+}
 
 // MP2 is not exercised by these drivers.
 int64_t mp2_workspace_bytes(int, int) { return 256; }

@@ -20,6 +20,10 @@
 //       failure isolation: some requests fail at admission (BQC_ENOMEM) or
 //       after their solve (BQC_EDEVICE) by injection, others are cancelled
 //       while queued; every other request's energy is unchanged.
+//   serving_stress batch
+//       bqc_t_energy_batch over fragments of mixed sizes (several rounds of
+//       triple batches, host and device inputs): every energy as predicted
+//       and equal to the fragment's bqc_t_energy_ex alone.
 //   serving_stress consumers
 //       two threads consume the same ticket at once (wait and poll); one
 //       gets the result, the other BQC_ENOTFOUND; then the server is
@@ -329,12 +333,14 @@ int run_faults(int direct) {
         Job& j = jobs[n];
         double e = 0;
         const int rc = bqc_t_wait(s, j.t, &e, nullptr);
-        int want = BQC_OK;
-        if (j.cancel_rc == BQC_OK) want = BQC_ECANCELED;  // cancelled while queued
-        else if (n % 7 == 3) want = BQC_ENOMEM;
+        int want = BQC_OK;  // the outcome had the request run
+        if (n % 7 == 3) want = BQC_ENOMEM;
         else if (n % 7 == 5) want = BQC_EDEVICE;
         if (j.cancel_rc != 99 && j.cancel_rc != BQC_OK && j.cancel_rc != BQC_PENDING) want = -100;
-        const bool good = rc == want && (rc != BQC_OK || e == expected_energy(j.o, j.eo));
+        // a cancel that returned BQC_OK either removed the queued request
+        // (BQC_ECANCELED) or found it finished already (its own outcome)
+        const bool was_cancelled = j.cancel_rc == BQC_OK && rc == BQC_ECANCELED;
+        const bool good = was_cancelled || (rc == want && (rc != BQC_OK || e == expected_energy(j.o, j.eo)));
         if (!good) {
             std::printf("faults: request %d rc %d (want %d) energy %.17g (want %.17g) cancel %d\n", n, rc, want, e,
                         expected_energy(j.o, j.eo), j.cancel_rc);
@@ -352,6 +358,65 @@ int run_faults(int direct) {
     std::printf("faults: ok %d cancelled %d enomem %d edevice %d bad %d\n", ok, cancelled, enomem, edevice, bad);
     std::fflush(stdout);
     return bad != 0 || cancelled == 0 || enomem == 0 || edevice == 0;
+}
+
+// --------------------------------------------------------------- batch
+int run_batch() {
+    int bad = 0;
+    const int shapes[][2] = {{12, 120}, {3, 20}, {1, 9}, {12, 118}, {6, 30}, {11, 120}, {8, 60}, {2, 17}};
+    const int n = (int)(sizeof(shapes) / sizeof(shapes[0]));
+    for (int dev = 0; dev < 2; ++dev) {
+        std::vector<std::vector<double>> eo(n), ev(n), big(n);
+        std::vector<void*> dmem;
+        std::vector<bqc_t_fragment> fr(n);
+        for (int f = 0; f < n; ++f) {
+            const int o = shapes[f][0], v = shapes[f][1];
+            eo[f] = occ_energies(o, 700 + f);
+            ev[f].assign(v, 0.4 + 0.001 * f);
+            const size_t nbig = (size_t)o * v * v * v + (size_t)o * o * v * v + (size_t)o * o * o * v;
+            const double *pe = eo[f].data(), *pv = ev[f].data(), *pz;
+            if (dev) {
+                void* a = nullptr;
+                void* b = nullptr;
+                void* c = nullptr;
+                (void)hipMalloc(&a, o * 8);
+                (void)hipMalloc(&b, v * 8);
+                (void)hipMalloc(&c, nbig * 8);
+                std::memcpy(a, pe, o * 8);
+                std::memcpy(b, pv, v * 8);
+                dmem.push_back(a); dmem.push_back(b); dmem.push_back(c);
+                pe = (const double*)a; pv = (const double*)b; pz = (const double*)c;
+            } else {
+                big[f].assign(nbig, 0.0);
+                pz = big[f].data();
+            }
+            fr[f] = bqc_t_fragment{o, v, pe, pv, pz, pz, pz, pz, pz};
+        }
+        bqc_t_opts op{};
+        op.precision = BQC_PREC_BF16X3;
+        op.inputs_on_device = dev;
+        std::vector<double> e(n, -1.0);
+        bqc_t_stats st{};
+        const int rc = bqc_t_energy_batch(n, fr.data(), &op, e.data(), &st);
+        if (rc != 0) { std::printf("batch failed %d: %s\n", rc, bqc_last_error()); return 1; }
+        for (int f = 0; f < n; ++f) {
+            const double want = expected_energy(shapes[f][0], eo[f]);
+            double alone = 0;
+            const bqc_t_fragment& x = fr[f];
+            const int rc2 = bqc_t_energy_ex(x.nocc, x.nvir, x.eps_o, x.eps_v, x.t1, x.t2, x.ovvv, x.ooov, x.ovov, &op,
+                                            &alone, nullptr);
+            if (e[f] != want || rc2 != 0 || alone != e[f]) {
+                std::printf("batch fragment %d (%d, %d): %.17g, alone %.17g, want %.17g\n", f, x.nocc, x.nvir, e[f],
+                            alone, want);
+                ++bad;
+            }
+        }
+        if (st.epilogue_launches < 2) { std::printf("batch ran in one round\n"); ++bad; }
+        for (void* p : dmem) (void)hipFree(p);
+    }
+    std::printf("batch: bad %d\n", bad);
+    std::fflush(stdout);
+    return bad != 0;
 }
 
 // --------------------------------------------------------------- consumers
@@ -427,6 +492,7 @@ int main(int argc, char** argv) {
     const std::string mode = argv[1];
     if (mode == "threads") return run_threads();
     if (mode == "consumers") return run_consumers();
+    if (mode == "batch") return run_batch();
     if (mode == "faults" && argc >= 3) return run_faults(std::atoi(argv[2]));
     if (mode == "stream" && argc >= 4) return run_stream(argv[2], std::atoi(argv[3]), argc > 4 ? std::atoi(argv[4]) : 0);
     std::printf("bad arguments\n");

@@ -275,3 +275,45 @@ def test_noalloc_batch_query():
     assert bqc.noalloc_batch(32, 300, "bf16x3") == 0     # (ia|bc) alone exceeds the array
     assert bqc.noalloc_batch(6, 30, "fp8", "virtual") == -1
     assert bqc.noalloc_batch(0, 30, "fp64") == -1
+
+
+def test_batch_argument_checks():
+    """bqc_t_energy_batch rejects bad arguments before any device work."""
+    import ctypes
+
+    import numpy as np
+
+    import paper_2502_17963_amd as bqc
+    from paper_2502_17963_amd.binding import Fragment, TOpts, TStats
+    from synth import make_inputs
+    L = bqc.lib()
+    x = make_inputs(3, 5, 10, 0)
+    arrs = [np.ascontiguousarray(a) for a in x.arrays()]
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def frag(o, v, a):
+        f = Fragment()
+        f.nocc, f.nvir = o, v
+        for name, arr in zip(("eps_o", "eps_v", "t1", "t2", "ovvv", "ooov", "ovov"), a):
+            setattr(f, name, arr.ctypes.data_as(dp))
+        return f
+
+    e = (ctypes.c_double * 4)()
+    good = (Fragment * 2)(frag(3, 5, arrs), frag(3, 5, arrs))
+    assert L.bqc_t_energy_batch(0, None, None, None, None) == 0
+    assert L.bqc_t_energy_batch(-1, good, None, e, None) == -1
+    assert L.bqc_t_energy_batch(2, None, None, e, None) == -1
+    assert L.bqc_t_energy_batch(2, good, None, None, None) == -1
+    bad = (Fragment * 2)(frag(3, 5, arrs), frag(0, 5, arrs))
+    assert L.bqc_t_energy_batch(2, bad, None, e, None) == -1
+    assert "fragment 1" in bqc.last_error()
+    eo_bad = arrs[0].copy()
+    eo_bad[0] = 5.0  # above every virtual energy: no gap
+    gap = (Fragment * 2)(frag(3, 5, arrs), frag(3, 5, [eo_bad] + arrs[1:]))
+    assert L.bqc_t_energy_batch(2, gap, None, e, None) == -1
+    for field, val in [("formulation", 1), ("triple_end", 3), ("precision", 7)]:
+        o = TOpts()
+        setattr(o, field, val)
+        assert L.bqc_t_energy_batch(2, good, ctypes.byref(o), e, ctypes.byref(TStats())) == -1, field
+    assert bqc.batch_footprint([(6, 30), (4, 20)], "bf16x3") > bqc.batch_footprint([(6, 30)], "bf16x3") > 0
+    assert bqc.batch_footprint([(0, 30)]) == -1

@@ -62,7 +62,8 @@ def test_server_host_logic_under_sanitizer(sanitizer, tmp_path):
 @pytest.fixture(scope="module", params=["address", "thread"])
 def serving_exe(request, tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("serving") / f"serving_stress_{request.param}")
-    _compile(["-x", "c++", os.path.join(SRC, "solve.hip"), "-x", "none", os.path.join(SRC, "server.cpp"),
+    _compile(["-x", "c++", os.path.join(SRC, "solve.hip"), os.path.join(SRC, "batch.hip"), "-x", "none",
+              os.path.join(SRC, "server.cpp"),
               os.path.join(SRC, "abi.cpp"), os.path.join(SRC, "sizes.cpp"), os.path.join(HERE, "mock_hip.cpp"),
               os.path.join(HERE, "mock_kernels.cpp"), os.path.join(HERE, "serving_stress.cpp")], exe,
              request.param)
@@ -107,3 +108,12 @@ def test_serving_failure_isolation(serving_exe):
     for direct in ("0", "1"):
         out = _run([exe, "faults", direct])
         assert "bad 0" in out and "faults: ok" in out, out[-2000:]
+
+
+def test_batch_driver(serving_exe):
+    """bqc_t_energy_batch's host driver (batch plan, tables, grouped-launch
+    entries of every round) on the stand-in runtime: fragments of mixed
+    sizes in several rounds, host and device inputs, every energy equal to
+    the fragment's solve alone."""
+    _, exe = serving_exe
+    assert "batch: bad 0" in _run([exe, "batch"])
