@@ -315,6 +315,12 @@ typedef struct {
     int32_t  direct_launch;    /* 0: each request's triple-batch launch sequence is built as one hipGraph
                                   (kernel nodes, no stream capture) and launched as a unit; 1: kernels
                                   are launched one by one on the slot's two streams */
+    int32_t  no_grouping;      /* 0: a slot that admits a small request (at most 5e11 algorithmic flops,
+                                  a few milliseconds of contraction) also admits up to 31 more queued
+                                  small ones that fit the arena together and runs them as one batch
+                                  (bqc_t_energy_batch's grouped launches; each result is bitwise the
+                                  request's alone; a failure of the batch is every member's);
+                                  1: one request per slot */
 } bqc_server_cfg;
 
 /* Creates a server; *out is written on BQC_OK. */

@@ -60,7 +60,7 @@ class Fragment(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("mem_budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_int32),
-                ("direct_launch", ctypes.c_int32)]
+                ("direct_launch", ctypes.c_int32), ("no_grouping", ctypes.c_int32)]
 
 
 class BqcError(RuntimeError):
@@ -419,9 +419,10 @@ class Server:
     status (the C ABI borrows them until then).
     """
 
-    def __init__(self, precision="fp64", device=0, mem_budget_bytes=0, max_inflight=0, graphs=True):
+    def __init__(self, precision="fp64", device=0, mem_budget_bytes=0, max_inflight=0, graphs=True, grouping=True):
         cfg = ServerCfg()
         cfg.direct_launch = 0 if graphs else 1
+        cfg.no_grouping = 0 if grouping else 1
         cfg.device = device
         cfg.precision = _prec(precision)
         cfg.mem_budget_bytes = int(mem_budget_bytes)

@@ -96,6 +96,7 @@ struct Request {
     bqc_t_stats stats{};
     clk::time_point t_submit, t_admit;
     size_t bytes = 0, off = 0;
+    size_t held = 0;  // bytes of the arena range this request holds from `off` (a group's range: its first member)
     int bypassed = 0;
     bool dev_in = false;  // inputs are device pointers read in place
     int fault_stage = 0, fault_code = 0;  // injected failure (host-side tests)
@@ -111,6 +112,7 @@ constexpr int FAULT_AFTER_SOLVE = 2;   // after its kernels have run, before its
 struct bqc_server {
     int device = 0, precision = 0, max_inflight = 4;
     bool graphs = true;  // run each request's launch sequence as one hipGraph
+    bool group = true;   // admit queued small requests together and run them as one batch
     uint64_t budget = 0;
     void* arena_base = nullptr;
     bqc::Arena* arena = nullptr;
@@ -184,6 +186,81 @@ int run_request(bqc_server* s, Request* r, hipStream_t st, hipStream_t side, dou
     return BQC_OK;
 }
 
+// Small requests may be admitted together and run as one batch (grouped
+// launches, batch.hip): requests of at most kGroupFlops algorithmic flops
+// (a few milliseconds of contraction, where launch overhead is a large
+// share), at most kGroupMax of them.  Each result is bitwise the one the
+// request has alone.
+constexpr double kGroupFlops = 5e11;
+constexpr int kGroupMax = 32;
+
+// Device bytes a group needs: the host-input members' inputs and the batch
+// workspace.
+size_t group_bytes(bqc_server* s, const std::vector<Request*>& g) {
+    std::vector<int> o, v;
+    size_t in = 0;
+    for (Request* r : g) {
+        o.push_back(r->o);
+        v.push_back(r->v);
+        if (!r->dev_in) in += a256((size_t)input_bytes(r->o, r->v));
+    }
+    return in + a256(plan_batch((int)g.size(), o.data(), v.data(), s->precision).total);
+}
+
+// Runs an admitted group of requests as one batch on the slot's stream.
+void run_group(bqc_server* s, const std::vector<Request*>& g, hipStream_t st) {
+    const int n = (int)g.size();
+    char* p = (char*)s->arena_base + g[0]->off;
+    std::vector<DevInputs> ins(n);
+    std::vector<int> o(n), v(n);
+    const auto u0 = clk::now();
+    bool uploaded = false;
+    for (int f = 0; f < n; ++f) {
+        Request* r = g[f];
+        o[f] = r->o;
+        v[f] = r->v;
+        const double* dst[7];
+        if (r->dev_in) {
+            for (int a = 0; a < 7; ++a) dst[a] = r->src[a];
+        } else {
+            const size_t sizes[7] = {(size_t)r->o, (size_t)r->v, (size_t)r->o * r->v, (size_t)r->o * r->o * r->v * r->v,
+                                     (size_t)r->o * r->v * r->v * r->v, (size_t)r->o * r->o * r->o * r->v,
+                                     (size_t)r->o * r->v * r->o * r->v};
+            char* q = p;
+            for (int a = 0; a < 7; ++a) {
+                BQC_HIP(hipMemcpyAsync(q, r->src[a], sizes[a] * sizeof(double), hipMemcpyHostToDevice, st));
+                dst[a] = (const double*)q;
+                q += a256(sizes[a] * sizeof(double));
+            }
+            p += a256((size_t)input_bytes(r->o, r->v));
+            uploaded = true;
+        }
+        DevInputs& in = ins[f];
+        in.o = r->o; in.v = r->v;
+        in.eps_o = dst[0]; in.eps_v = dst[1]; in.t1 = dst[2]; in.t2 = dst[3];
+        in.ovvv = dst[4]; in.ooov = dst[5]; in.ovov = dst[6];
+    }
+    if (uploaded) BQC_HIP(hipStreamSynchronize(st));
+    const double upload_s = std::chrono::duration<double>(clk::now() - u0).count();
+    const BatchPlan bp = plan_batch(n, o.data(), v.data(), s->precision);
+    std::vector<double> e(n);
+    SolveStats ss;
+    enqueue_batch(bp, s->precision, n, ins.data(), p, st, e.data(), &ss);
+    for (int f = 0; f < n; ++f) {
+        Request* r = g[f];
+        if (!std::isfinite(e[f])) throw Error(BQC_EDEVICE, "non-finite energy");
+        r->energy = e[f];
+        r->stats.upload_s = upload_s;
+        r->stats.gpu_s = ss.gpu_s;
+        r->stats.footprint_bytes = g[0]->held;
+        r->stats.flops = 12.0 * (double)num_triples(r->o) * (double)r->v * r->v * r->v * (double)(r->v + r->o);
+        r->stats.precision = s->precision;
+        r->stats.n_triples = (int32_t)num_triples(r->o);
+        r->stats.gemm_launches = ss.gemm_launches;
+        r->stats.epilogue_launches = ss.epi_launches;
+    }
+}
+
 // Picks the request to admit (caller holds s->mu); nullptr if none fits.
 Request* admit_locked(bqc_server* s) {
     for (size_t q = 0; q < s->queue.size(); ++q) {
@@ -191,6 +268,7 @@ Request* admit_locked(bqc_server* s) {
         size_t off = 0;
         if (s->arena->alloc(r->bytes, &off)) {
             r->off = off;
+            r->held = r->bytes;
             auto f = s->faults.find(r->ticket);
             if (f != s->faults.end()) {
                 r->fault_stage = f->second.first;
@@ -206,29 +284,81 @@ Request* admit_locked(bqc_server* s) {
     return nullptr;
 }
 
+// The request to admit and, if it is small, the queued small requests that
+// join it (caller holds s->mu).  The group holds one arena range (its first
+// member's `off` / `held`); empty if nothing fits.
+std::vector<Request*> admit_group_locked(bqc_server* s) {
+    Request* r = admit_locked(s);
+    if (!r) return {};
+    auto small = [&](Request* q) {
+        const double fl = 12.0 * (double)num_triples(q->o) * (double)q->v * q->v * q->v * (double)(q->v + q->o);
+        return fl <= kGroupFlops && q->fault_stage == 0 && s->faults.find(q->ticket) == s->faults.end();
+    };
+    if (!s->group || !small(r)) return {r};
+    std::vector<Request*> cand{r};
+    for (Request* q : s->queue) {
+        if ((int)cand.size() >= kGroupMax) break;
+        if (small(q)) cand.push_back(q);
+        else if (q->bypassed >= kMaxBypass) break;  // take no memory a starved request waits for
+    }
+    if (cand.size() == 1) return {r};
+    // the largest prefix of the candidates whose batch fits the arena
+    s->arena->release(r->off, r->held);
+    for (size_t k = cand.size(); k >= 2; --k) {
+        std::vector<Request*> g(cand.begin(), cand.begin() + k);
+        const size_t bytes = group_bytes(s, g);
+        size_t off = 0;
+        if (s->arena->alloc(bytes, &off)) {
+            for (size_t m = 1; m < k; ++m) {
+                auto it = std::find(s->queue.begin(), s->queue.end(), g[m]);
+                s->queue.erase(it);
+                g[m]->off = 0;
+                g[m]->held = 0;
+            }
+            r->off = off;
+            r->held = bytes;
+            return g;
+        }
+    }
+    size_t off = 0;  // alone after all (the range it held is free again)
+    if (!s->arena->alloc(r->bytes, &off)) throw Error(BQC_ENOMEM, "arena state changed during admission");
+    r->off = off;
+    r->held = r->bytes;
+    return {r};
+}
+
 void slot_main(bqc_server* s, int idx) {
     (void)hipSetDevice(s->device);
     hipStream_t st = s->streams[idx];
     hipStream_t side = s->sides[idx];
     double* pinned = s->pinned[idx];
     for (;;) {
-        Request* r = nullptr;
+        std::vector<Request*> grp;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
                 if (s->stop && s->queue.empty()) return;
-                r = admit_locked(s);
-                if (r) break;
+                grp = admit_group_locked(s);
+                if (!grp.empty()) break;
                 s->cv_work.wait(lk);
             }
-            r->state = St::Running;
-            r->t_admit = clk::now();
+            const auto now = clk::now();
+            for (Request* q : grp) {
+                q->state = St::Running;
+                q->t_admit = now;
+            }
         }
+        Request* r = grp[0];
         int rc;
         std::string err;
         try {
             if (r->fault_stage == FAULT_AT_ADMISSION) throw Error(r->fault_code, "injected failure at admission");
-            rc = run_request(s, r, st, side, pinned);
+            if (grp.size() > 1) {
+                run_group(s, grp, st);
+                rc = BQC_OK;
+            } else {
+                rc = run_request(s, r, st, side, pinned);
+            }
         } catch (const Error& e) {
             rc = e.code;
             err = e.what();
@@ -247,13 +377,15 @@ void slot_main(bqc_server* s, int idx) {
         }
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            s->arena->release(r->off, r->bytes);
+            s->arena->release(r->off, r->held);
             const auto now = clk::now();
-            r->stats.queue_s = std::chrono::duration<double>(r->t_admit - r->t_submit).count();
-            r->stats.total_s = std::chrono::duration<double>(now - r->t_submit).count();
-            r->rc = rc;
-            r->err = err;
-            r->state = St::Done;
+            for (Request* q : grp) {  // a group shares its outcome
+                q->stats.queue_s = std::chrono::duration<double>(q->t_admit - q->t_submit).count();
+                q->stats.total_s = std::chrono::duration<double>(now - q->t_submit).count();
+                q->rc = rc;
+                q->err = err;
+                q->state = St::Done;
+            }
         }
         s->cv_work.notify_all();  // freed memory may admit queued requests
         s->cv_done.notify_all();
@@ -275,6 +407,7 @@ int create_impl(const bqc_server_cfg* cfg, bqc_server** out) {
     s->precision = cfg->precision;
     s->max_inflight = cfg->max_inflight > 0 ? cfg->max_inflight : 4;
     s->graphs = cfg->direct_launch == 0;
+    s->group = cfg->no_grouping == 0;
     try {
         size_t fr = 0, tot = 0;
         BQC_HIP(hipMemGetInfo(&fr, &tot));

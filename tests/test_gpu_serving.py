@@ -166,3 +166,29 @@ def test_cancel_queued_request():
         with pytest.raises(bqc.BqcError) as ei:
             srv.cancel(tickets[0])
         assert ei.value.code == -4
+
+
+@pytest.mark.parametrize("grouping", [True, False])
+def test_small_requests_grouped_into_batches(grouping):
+    """One slot and a queue of small requests: with grouping the slot admits
+    several at once and runs them as one batch (grouped launches); every
+    result is bitwise the request's alone either way."""
+    bqc = _bqc()
+    print(f"case serving grouping={grouping}", flush=True)
+    shapes = [(3, 20, 40, 601), (4, 25, 50, 602), (2, 30, 40, 603), (5, 22, 60, 604), (6, 30, 120, 605),
+              (3, 17, 30, 606), (4, 45, 90, 607), (7, 33, 100, 608), (1, 9, 20, 609), (8, 24, 80, 610),
+              (5, 37, 100, 611), (2, 50, 60, 612)]
+    xs = [make_inputs(*s) for s in shapes]
+    alone = [bqc.t_energy(s[0], s[1], *x.arrays(), precision="bf16x3") for s, x in zip(shapes, xs)]
+    with bqc.Server(precision="bf16x3", max_inflight=1, mem_budget_bytes=4 << 30, grouping=grouping) as srv:
+        tickets = [srv.submit(s[0], s[1], *x.arrays()) for s, x in zip(shapes, xs)]
+        res = [srv.wait(t) for t in tickets]
+    grouped = 0
+    for k, (e, st) in enumerate(res):
+        assert e == alone[k], (shapes[k], e, alone[k])
+        grouped += st["gemm_launches"] > 0  # set for requests that ran in a batch
+    print(f"  {grouped} of {len(shapes)} requests ran in batches", flush=True)
+    if grouping:
+        assert grouped >= 2
+    else:
+        assert grouped == 0
