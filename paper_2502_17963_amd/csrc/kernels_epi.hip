@@ -71,6 +71,12 @@ __device__ __forceinline__ void epilogue_body(const EpiLaunch& e, int orb, int t
     auto blk = [&](const HT* H, int X, int Y, int Z) { return H + (((int64_t)X * nt + Y) * nt + Z) * E_T3; };
 
     constexpr int T = EPI_T, T2 = EPI_T * EPI_T;
+    // LDS layouts, XOR-swizzled so that the permuted reads of phase 3 meet
+    // at most two addresses per bank (eight without): W element (x, y, z) of
+    // a tile permutation at x T2 + (y ^ x) T + (z ^ y), and element (x, y) of
+    // an 8 x 8 block of the singles (and f_ov) factors at x T + (y ^ x)
+    auto widx = [](int x, int y, int z) { return x * T2 + ((y ^ x) * T) + (z ^ y); };
+    auto gidx = [](int x, int y) { return x * T + (y ^ x); };
     __shared__ double Ws[6][E_T3];
     // singles-term factors of the orbit's tiles: G[m][X][Y][x][y] with
     // m = 0: (jb|kc), 1: (ia|kc), 2: (ia|jb), X, Y tile ids in {A, B, C};
@@ -166,21 +172,24 @@ __device__ __forceinline__ void epilogue_body(const EpiLaunch& e, int orb, int t
 #pragma unroll
     for (int n = 0; n < NG; ++n) {
         const int el = threadIdx.x + n * E_THREADS;
-        if (el < 27 * T2) (&Gs[0][0][0][0])[el] = gv[n];
+        if (el < 27 * T2) (&Gs[0][0][0][0])[el - el % T2 + gidx(el % T2 / T, el % T)] = gv[n];
     }
     if (threadIdx.x < 9 * T) (&t1s[0][0][0])[threadIdx.x] = t1v;
     if constexpr (FOCK) {
 #pragma unroll
         for (int n = 0; n < NG; ++n) {
             const int el = threadIdx.x + n * E_THREADS;
-            if (el < 27 * T2) (&Ts[0][0][0][0])[el] = tv[n];
+            if (el < 27 * T2) (&Ts[0][0][0][0])[el - el % T2 + gidx(el % T2 / T, el % T)] = tv[n];
         }
         if (threadIdx.x < 9 * T) (&fs[0][0][0])[threadIdx.x] = fv;
     }
 #pragma unroll
     for (int s = 0; s < 6; ++s)
 #pragma unroll
-        for (int n = 0; n < NE; ++n) Ws[s][threadIdx.x + n * E_THREADS] = wv[s][n];
+        for (int n = 0; n < NE; ++n) {
+            const int el = threadIdx.x + n * E_THREADS;
+            Ws[s][widx(el / T2, (el / T) % T, el % T)] = wv[s][n];
+        }
     __syncthreads();
 
     // phase 3: one element (a, b, c) of the base tile and its six permutations
@@ -191,17 +200,23 @@ __device__ __forceinline__ void epilogue_body(const EpiLaunch& e, int orb, int t
         const int a = TT[0] * T + l[0], b = TT[1] * T + l[1], c = TT[2] * T + l[2];
         if (a >= v || b >= v || c >= v) continue;
         double W[6], V[6];
+        // t_{i,j,k} at the element's three virtuals (tile id A, local l[A])
+        double tv[3][3];
+#pragma unroll
+        for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int A = 0; A < 3; ++A) tv[n][A] = t1s[n][A][l[A]];
 #pragma unroll
         for (int p = 0; p < 6; ++p) {
             // permutation p puts tile ids (X, Y, Z) on the virtual slots a, b, c
             const int X = perm[p][0], Y = perm[p][1], Z = perm[p][2];
             const int x = l[X], y = l[Y], z = l[Z];
-            W[p] = Ws[p][(x * T + y) * T + z];
-            V[p] = W[p] + t1s[0][X][x] * Gs[0][Y][Z][y * T + z] + t1s[1][Y][y] * Gs[1][X][Z][x * T + z] +
-                   t1s[2][Z][z] * Gs[2][X][Y][x * T + y];
+            W[p] = Ws[p][widx(x, y, z)];
+            V[p] = W[p] + tv[0][X] * Gs[0][Y][Z][gidx(y, z)] + tv[1][Y] * Gs[1][X][Z][gidx(x, z)] +
+                   tv[2][Z] * Gs[2][X][Y][gidx(x, y)];
             if constexpr (FOCK)
-                V[p] += fs[0][X][x] * Ts[0][Y][Z][y * T + z] + fs[1][Y][y] * Ts[1][X][Z][x * T + z] +
-                        fs[2][Z][z] * Ts[2][X][Y][x * T + y];
+                V[p] += fs[0][X][x] * Ts[0][Y][Z][gidx(y, z)] + fs[1][Y][y] * Ts[1][X][Z][gidx(x, z)] +
+                        fs[2][Z][z] * Ts[2][X][Y][gidx(x, y)];
         }
         const double d = eocc - e.eps_v[a] - e.eps_v[b] - e.eps_v[c];
         const double se = V[0] + V[3] + V[4], so = V[1] + V[2] + V[5];
