@@ -91,3 +91,25 @@ def test_virtual_loop_sampled_triples(largest):
         ref = virtual_triple_energy(a, b, c, m, *host)
         print(f"virtual triple {n} ({a},{b},{c}) gpu={gpu:.15e} oracle={ref:.15e}", flush=True)
         assert abs(gpu - ref) <= 1e-10 * abs(ref)
+
+
+@pytest.mark.gpu
+@pytest.mark.slow
+def test_host_inputs_at_full_size(largest):
+    """The host-pointer form of the entry point at the largest shape: the
+    library uploads the 51 GB of FP64 inputs itself and the energy of a
+    sampled triple equals the device-input solve's bit for bit, in FP64 and
+    in split-BF16x3."""
+    bqc, o, v, dev, host = largest
+    hin = [a.cpu().numpy() for a in dev]
+    nbytes = sum(a.nbytes for a in hin)
+    n = len(triple_table(o)) // 2
+    for prec in ("bf16x3", "fp64"):
+        e_dev, ex_d = bqc.t_energy(o, v, *dev, precision=prec, triple_energies=True, triple_range=(n, n + 1))
+        e_host, ex_h = bqc.t_energy(o, v, *hin, precision=prec, triple_energies=True, triple_range=(n, n + 1),
+                                    stats=True)
+        up = ex_h["stats"]["upload_s"]
+        print(f"{prec} triple {n}: device inputs {e_dev!r}, host inputs {e_host!r}; "
+              f"upload {nbytes / 1e9:.1f} GB in {up:.2f} s ({nbytes / up / 1e9:.1f} GB/s)", flush=True)
+        assert e_host == e_dev
+        assert ex_h["triples"][n] == ex_d["triples"][n]

@@ -4,7 +4,8 @@ FP64 contractions: |E_gpu - E_oracle| <= 1e-10 |E_oracle| (and every
 per-triple energy within 1e-10 of the largest one).  Mixed precision:
 |dE| <= 1 uEh on the small workload and relative error <= 1e-6 elsewhere
 (the synthetic energies grow far beyond 1 Eh at the larger shapes, where
-1 uEh is below the FP64 oracle's own rounding).
+1 uEh is far inside what the FP64 path's own 1e-10 relative target allows,
+e.g. 2.7e3 uEh at |E_T| = 2.7e7 Eh).
 """
 import json
 import os
