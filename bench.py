@@ -238,12 +238,12 @@ def run_serving(args):
 def stored_oracle(workload, seed, x):
     """The oracle's stored whole solve of a workload (E_T and per-triple
     energies), if it exists and was computed from these inputs, else None."""
-    from synth import fingerprint
+    from synth import summary_matches
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_seed{seed}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    return rec if rec.get("input_fingerprint") == fingerprint(x) else None
+    return rec if "input_summary" in rec and summary_matches(rec["input_summary"], x) else None
 
 
 def run_sweep(args):

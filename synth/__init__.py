@@ -263,14 +263,33 @@ def make_inputs_device(nocc: int, nvir: int, naux: int, seed: int, device="cuda:
     return tuple(a.contiguous() for a in (eps_o, eps_v, t1, t2, ovvv, ooov, ovov))
 
 
-def fingerprint(x) -> str:
-    """sha256 over the bytes of the orbital energies, t1 and a strided sample
-    (every 4099th element) of t2, (ia|bc), ooov and ovov of generated inputs
-    x: identifies the inputs a stored result was computed from."""
-    import hashlib
-    h = hashlib.sha256()
-    for a in (x.eps_o, x.eps_v, x.t1):
-        h.update(a.tobytes())
-    for a in (x.t2, x.ovvv, x.ooov, x.ovov):
-        h.update(a.reshape(-1)[::4099].tobytes())
-    return h.hexdigest()
+SUMMARY_ARRAYS = ("eps_o", "eps_v", "t1", "t2", "ovvv", "ooov", "ovov")
+
+
+def input_summary(x) -> dict:
+    """Identifies the inputs x a stored result was computed from: for each
+    array, over a strided sample (every 4099th element), the sum, the sum of
+    magnitudes and a sum weighted by (position mod 13) - 6 (which also sees
+    a reordering).  The integrals are BLAS products over Q, whose rounding
+    differs between machines in the last bits, so summaries are compared
+    with summary_matches, not for equality."""
+    out = {}
+    for name in SUMMARY_ARRAYS:
+        a = getattr(x, name).reshape(-1)[::4099]
+        w = (np.arange(a.size) % 13) - 6.0
+        out[name] = [float(a.sum()), float(np.abs(a).sum()), float(np.dot(w, a))]
+    return out
+
+
+def summary_matches(stored: dict, x, rel: float = 1e-12) -> bool:
+    """True when the inputs x have the stored summary up to rounding: every
+    sum within rel times six times the sample's sum of magnitudes (a
+    different draw or layout changes them at order one)."""
+    now = input_summary(x)
+    for name in SUMMARY_ARRAYS:
+        s0, m0, w0 = stored[name]
+        s1, m1, w1 = now[name]
+        tol = rel * 6.0 * max(m0, 1e-300)
+        if abs(s0 - s1) > tol or abs(m0 - m1) > tol or abs(w0 - w1) > tol:
+            return False
+    return True

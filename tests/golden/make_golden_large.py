@@ -10,10 +10,16 @@ Workloads: large_fragment, nocc = 32, nvir = 300, naux = 1000, seed 0
 (5952 unique triples, 6.4e14 flops; about two hours on eight host cores),
 and precision_sweep, nocc = 24, nvir = 240, naux = 800, seed 0 (2576
 triples, 1.1e14 flops).  Output: tests/golden/<workload>_seed0.json with
-E_T, every per-triple energy and a fingerprint of the generated inputs.
+E_T, every per-triple energy and a summary of the generated inputs
+(synth.input_summary).
 Run from the repository root:
 
     python tests/golden/make_golden_large.py [--workload NAME] [--workers N]
+
+With --summary-only, an existing file keeps its oracle values and gets the
+input summary of freshly generated inputs (the summary replaced an exact
+hash of the inputs, which differs between machines in the last bits of the
+BLAS products).
 """
 import argparse
 import json
@@ -32,7 +38,7 @@ sys.path.insert(0, ROOT)
 import multiprocessing as mp  # noqa: E402
 
 from oracle.closed_shell import triple_energy, triple_table  # noqa: E402
-from synth import fingerprint, make_inputs  # noqa: E402
+from synth import input_summary, make_inputs  # noqa: E402
 
 SHAPES = {"large_fragment": (32, 300, 1000, 0), "precision_sweep": (24, 240, 800, 0)}
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,11 +56,22 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=max(1, (os.cpu_count() or 2) - 2))
     ap.add_argument("--workload", default="large_fragment", choices=sorted(SHAPES))
+    ap.add_argument("--summary-only", action="store_true")
     a = ap.parse_args()
     o, v, naux, seed = SHAPES[a.workload]
     out_path = os.path.join(HERE, f"{a.workload}_seed{seed}.json")
     t0 = time.time()
     _X = make_inputs(o, v, naux, seed)
+    if a.summary_only:
+        rec = json.load(open(out_path))
+        rec.pop("input_fingerprint", None)
+        rec = {**{k: rec[k] for k in ("nocc", "nvir", "naux", "seed", "generator", "oracle")},
+               "input_summary": input_summary(_X), "E_T": rec["E_T"], "triples": rec["triples"]}
+        with open(out_path, "w") as f:
+            json.dump(rec, f)
+            f.write("\n")
+        print(f"summary of {out_path} rewritten", flush=True)
+        return
     table = triple_table(o)
     print(f"inputs in {time.time() - t0:.0f} s; {len(table)} triples on {a.workers} workers", flush=True)
     terms = [None] * len(table)
@@ -71,7 +88,7 @@ def main():
     e_t = math.fsum(terms)
     rec = {"nocc": o, "nvir": v, "naux": naux, "seed": seed, "generator": "synth.make_inputs",
            "oracle": "oracle.closed_shell.triple_energy per unique triple, math.fsum over triples",
-           "input_fingerprint": fingerprint(_X), "E_T": e_t, "triples": terms}
+           "input_summary": input_summary(_X), "E_T": e_t, "triples": terms}
     with open(out_path, "w") as f:
         json.dump(rec, f)
         f.write("\n")

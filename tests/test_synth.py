@@ -59,3 +59,26 @@ def test_serving_stream_shapes():
         assert 6 * r["nocc"] - 1 <= r["nvir"] <= 10 * r["nocc"] + 1
         assert r["naux"] == round(3.3 * (r["nocc"] + r["nvir"]))
     assert serving_stream(16) == serving_stream(256)[:16]
+
+
+def test_input_summary_tolerates_rounding_only():
+    """The stored-input summary matches the same draw with the integrals
+    perturbed in the last bits (as another machine's BLAS rounds them), and
+    rejects another seed, a transposed array and a one-element change."""
+    import dataclasses
+
+    import numpy as np
+
+    from synth import input_summary, make_inputs, summary_matches
+    x = make_inputs(6, 40, 100, 3)
+    ref = input_summary(x)
+    assert summary_matches(ref, x)
+    ulp = dataclasses.replace(x, ovvv=x.ovvv * (1.0 + 2.0 ** -52 * np.sign(np.sin(np.arange(x.ovvv.size)))
+                                                .reshape(x.ovvv.shape)))
+    assert summary_matches(ref, ulp)
+    assert not summary_matches(ref, make_inputs(6, 40, 100, 4))
+    tr = dataclasses.replace(x, ovov=np.ascontiguousarray(x.ovov.transpose(0, 3, 2, 1)))
+    assert not summary_matches(ref, tr)
+    one = x.t2.copy()
+    one.reshape(-1)[0] += 1e-6
+    assert not summary_matches(ref, dataclasses.replace(x, t2=one))
