@@ -250,6 +250,7 @@ def run_sweep(args):
     """Every contraction precision on the whole solve of one workload (FP64
     denominators and compensated sums in all of them): seconds per solve,
     TFLOP/s and |dE_T| against the oracle's stored whole solve."""
+    import numpy as np
     import torch
 
     import paper_2502_17963_amd as bqc
@@ -276,6 +277,10 @@ def run_sweep(args):
         if ref is not None:
             r["dE_uEh_vs_oracle"] = abs(e - ref["E_T"]) * 1e6
             r["rel_vs_oracle"] = abs(e - ref["E_T"]) / abs(ref["E_T"])
+            # per-triple energies of an untimed solve against the stored ones
+            _, ex = bqc.t_energy(o, v, *dev, precision=prec, triple_energies=True)
+            rt = np.asarray(ref["triples"])
+            r["worst_triple_rel_vs_oracle"] = float(np.max(np.abs(ex["triples"] - rt)) / np.max(np.abs(rt)))
         recs[prec] = r
         print(f"[sweep] {prec}: E_T={e:.12e} {dt:.3f} s {r['tflops']} TFLOP/s "
               f"dE={r.get('dE_uEh_vs_oracle', float('nan')):.3e} uEh", file=sys.stderr, flush=True)

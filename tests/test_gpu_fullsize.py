@@ -1,4 +1,5 @@
-"""Parity at the benchmarked size (nocc=32, nvir=300, naux=1000, seed 0).
+"""Parity at the benchmarked sizes (nocc=32, nvir=300, naux=1000, seed 0, and
+the precision-sweep workload nocc=24, nvir=240, naux=800, seed 0).
 
 The oracle's whole solve of this workload is stored
 (tests/golden/large_fragment_seed0.json, written by
@@ -147,3 +148,34 @@ def test_virtual_formulation_sampled_triples_and_total(large):
     e_b = bqc.t_energy(o, v, *dev, precision="bf16x3", formulation="virtual")
     torch.cuda.synchronize()
     assert abs(e_b - e64) <= 1e-6 * abs(e64)
+
+
+def test_precision_sweep_every_triple_matches_stored_oracle():
+    """The precision-sweep workload (nocc=24, nvir=240, naux=800, seed 0)
+    against the oracle's stored whole solve
+    (tests/golden/precision_sweep_seed0.json): every per-triple energy and
+    E_T at 1e-10 in FP64, the FP32 and split-BF16x3 totals at 1e-6."""
+    import torch
+
+    import paper_2502_17963_amd as bqc
+    path = os.path.join(os.path.dirname(__file__), "golden", "precision_sweep_seed0.json")
+    if not os.path.exists(path):
+        pytest.skip("the oracle's whole solve of the precision-sweep workload has not been stored")
+    o, v, naux, seed = CONFIGS["precision_sweep"]
+    print(f"case precision_sweep o={o} v={v} naux={naux} seed={seed}", flush=True)
+    x = make_inputs(o, v, naux, seed)
+    rec = json.load(open(path))
+    assert summary_matches(rec["input_summary"], x), "the generator no longer makes the stored inputs"
+    dev = [torch.from_numpy(a).to("cuda:0") for a in x.arrays()]
+    e64, ex = bqc.t_energy(o, v, *dev, precision="fp64", triple_energies=True)
+    ref = np.array(rec["triples"])
+    worst = np.max(np.abs(ex["triples"] - ref)) / np.max(np.abs(ref))
+    rel = abs(e64 - rec["E_T"]) / abs(rec["E_T"])
+    print(f"fp64 E={e64:.15e} oracle={rec['E_T']:.15e} rel={rel:.3e} worst triple {worst:.3e}", flush=True)
+    assert worst <= 1e-10 and rel <= 1e-10
+    for prec in ("fp32", "bf16x3"):
+        e = bqc.t_energy(o, v, *dev, precision=prec)
+        rel = abs(e - rec["E_T"]) / abs(rec["E_T"])
+        print(f"{prec} E={e:.12e} rel={rel:.3e} dE={abs(e - rec['E_T']) * 1e6:.3e} uEh", flush=True)
+        assert rel <= 1e-6
+    torch.cuda.synchronize()
