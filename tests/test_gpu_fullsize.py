@@ -1,8 +1,8 @@
 """Parity at the benchmarked sizes (nocc=32, nvir=300, naux=1000, seed 0, and
 the precision-sweep workload nocc=24, nvir=240, naux=800, seed 0).
 
-The oracle's whole solve of this workload is stored
-(tests/golden/large_fragment_seed0.json, written by
+The oracle's whole solve of each workload is stored
+(tests/golden/<workload>_seed0.json, written by
 tests/golden/make_golden_large.py, which calls only the oracle and the
 generator): the GPU's FP64 per-triple energies are compared with it triple
 by triple and in total, and the mixed-precision totals with its total, in
