@@ -425,7 +425,7 @@ def run_copy_calibration(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding of the "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; multi-GPU sharding of the "
                           "triple blocks is a design note, not implemented"}))
         sys.exit(2)
     if args.workload == "serving":
