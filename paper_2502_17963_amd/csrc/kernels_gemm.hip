@@ -292,6 +292,41 @@ __device__ __forceinline__ void stage_products(typename Mode<PREC>::Acc (&acc)[W
 
 // The work of logical work group L of one contraction launch of g (the
 // launch's tiles are nblk 16-blocks split into ntile_u x ntile_w tiles).
+// Store of a wave's WB x WB accumulator blocks into one plane of a blocked H
+// buffer (element (u, w) of the plane at out + (u / 8) nt 512 + (u % 8) 8 +
+// (w / 8) 512 + w % 8) when the whole wave tile lies inside the plane and
+// the plane's offsets fit 32 bits: one byte offset per lane and row slot r,
+// stepped by block (uniform strides), and no masks.  Returns false (nothing
+// stored) otherwise; the caller then stores element by element.
+template <class M, int WB, class Acc, class HT>
+__device__ __forceinline__ bool store_tile_fast(const Acc (&acc)[WB][WB], HT* out, int n, int nt, int u00, int w00,
+                                                int wun, int wwn, int lane) {
+    const int64_t rowblk = (int64_t)nt * 512;  // elements from one 8-row group to the next
+    const bool full = wun == WB && wwn == WB && u00 + 16 * WB <= n && w00 + 16 * WB <= n &&
+                      (int64_t)nt * nt * 512 * (int64_t)sizeof(HT) < ((int64_t)1 << 31);
+    if (!full) return false;
+    const int fr = lane & 15;
+    const int w = w00 + fr;
+    const uint32_t wbyte = (uint32_t)(((w >> 3) * 512 + (w & 7)) * (int)sizeof(HT));
+    uint32_t roff[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int u = u00 + M::row(lane, r);
+        roff[r] = (uint32_t)(((u >> 3) * rowblk + (u & 7) * 8) * (int64_t)sizeof(HT)) + wbyte;
+    }
+    const uint32_t mstep = (uint32_t)(2 * rowblk * (int64_t)sizeof(HT));  // 16 rows
+    constexpr uint32_t nstep = 2 * 512 * sizeof(HT);                      // 16 columns
+    char* base = (char*)out;
+#pragma unroll
+    for (int m = 0; m < WB; ++m)
+#pragma unroll
+        for (int nn = 0; nn < WB; ++nn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                *(HT*)(base + (roff[r] + m * mstep + nn * nstep)) = (HT)acc[m][nn][r];
+    return true;
+}
+
 template <int PREC, class G, int FORM>
 __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk, int ntile_u, int ntile_w) {
     constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, NVEC = G::NVEC, WB = G::WB;
@@ -439,6 +474,7 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
     HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(n) +
               (int64_t)(y >> 3) * nt * nt * 512 + (y & 7) * 64;
     const int u00 = (ub + wub) * 16, w00 = (wb + wwb) * 16;
+    if (store_tile_fast<M, WB>(acc, out, n, nt, u00, w00, wun, wwn, lane)) return;
 #pragma unroll
     for (int m = 0; m < WB; ++m)
 #pragma unroll
@@ -610,6 +646,7 @@ __global__ __launch_bounds__(64 * PL_NP, 1) void h_gemm_planes_kernel(GemmLaunch
     const int nt = ceil_div(n, EPI_T);
     HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(n) + (int64_t)(y >> 3) * nt * nt * 512 +
               (y & 7) * 64;
+    if (store_tile_fast<M, WB>(acc, out, n, nt, 0, 0, WB, WB, lane)) return;
 #pragma unroll
     for (int m = 0; m < WB; ++m)
 #pragma unroll
