@@ -338,17 +338,22 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
     const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
     // size of the space the planes, rows and columns of H run over
     const int n = FORM == FORM_VIR ? o : v;
+    // The work-group indices are uniform; the integer divisions that decode
+    // them leave their results in vector registers, so they are moved back to
+    // scalar registers (then every operand address of the chunk loop is
+    // scalar arithmetic plus one 32-bit lane offset).
     int rem = L;
-    const int tw = rem % ntile_w; rem /= ntile_w;
-    const int tu = rem % ntile_u; rem /= ntile_u;
+    const int tw = __builtin_amdgcn_readfirstlane(rem % ntile_w); rem /= ntile_w;
+    const int tu = __builtin_amdgcn_readfirstlane(rem % ntile_u); rem /= ntile_u;
     // the three pairs of a plane are neighbours: they share the plane's
     // (ov|vv) rows of i, j and k in L2 (half the HBM fetch of pair-major order)
-    const int h = rem % 3; rem /= 3;
-    const int y = rem % n;
-    const int t = rem / n;
+    const int h = __builtin_amdgcn_readfirstlane(rem % 3); rem /= 3;
+    const int y = __builtin_amdgcn_readfirstlane(rem % n);
+    const int t = __builtin_amdgcn_readfirstlane(rem / n);
     const int4 tr = g.trip[t];
     int q, P, R;
-    roles(h, tr.x, tr.y, tr.z, q, P, R);
+    roles(h, __builtin_amdgcn_readfirstlane(tr.x), __builtin_amdgcn_readfirstlane(tr.y),
+          __builtin_amdgcn_readfirstlane(tr.z), q, P, R);
 
     int ub, un, wb, wn;  // tile block start / count along u and w
     tile_range(tu, nblk, ntile_u, ub, un);
@@ -375,18 +380,21 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
     // This thread's 16-byte vector qv of each staged row, and its rows: vector
     // e covers LDS row (tid / 8) + e NTHR / 8; rows [0, TILE_U) hold the Row
     // factor (u), rows [TILE_U, NROW) the Col factor (w).  Byte offsets
-    // within a chunk block are fixed for the work group.
+    // within a chunk block are fixed for the work group, and vector e of
+    // every thread lies on the same side (TILE_U is a multiple of NTHR / 8).
+    // Rows past the operand's last row, or past the tile's blocks,
+    // read the operand's last row: their products land only in rows or
+    // columns of H that are not stored, so every load is unconditional.
+    static_assert(TILE_U % (NTHR / 8) == 0, "each staging vector stays on one side");
     const int qv = tid & 7;
-    int off[NVEC];
-    bool ok[NVEC], isrow[NVEC];
+    uint32_t off[NVEC];
+    constexpr auto isrow = [](int e) { return e * (NTHR / 8) < TILE_U; };
 #pragma unroll
     for (int e = 0; e < NVEC; ++e) {
         const int row = (tid >> 3) + e * (NTHR / 8);
-        isrow[e] = row < TILE_U;
-        const int r = isrow[e] ? row : row - TILE_U;
-        const int gr = (isrow[e] ? ub : wb) * 16 + r;
-        ok[e] = row < NROW && r < (isrow[e] ? un : wn) * 16 && gr < n;
-        off[e] = gr * ROWB + qv * 16;
+        const int r = isrow(e) ? row : row - TILE_U;
+        const int gr = min((isrow(e) ? ub : wb) * 16 + r, n - 1);
+        off[e] = (uint32_t)(gr * ROWB + qv * 16);
     }
 
     const int nch_v = Kv / KC, nch_o = Ko / KC;
@@ -425,10 +433,7 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
         const char* rb = arr_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * blk;
         const char* cb = arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * blk;
 #pragma unroll
-        for (int e = 0; e < NVEC; ++e) {
-            const char* base = isrow[e] ? rb : cb;
-            reg[e] = ok[e] ? *(const u4*)(base + off[e]) : u4{0, 0, 0, 0};
-        }
+        for (int e = 0; e < NVEC; ++e) reg[e] = *(const u4*)((isrow(e) ? rb : cb) + off[e]);
         if constexpr (PREC == 3) {
             const uint32_t* rs = scale_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * (int64_t)n;
             const uint32_t* cs = scale_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * (int64_t)n;
