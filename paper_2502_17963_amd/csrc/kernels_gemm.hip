@@ -399,12 +399,6 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
 
     const int nch_v = Kv / KC, nch_o = Ko / KC;
     const int nch = 2 * nch_v + 2 * nch_o;
-    auto chunk_seg = [&](int c, int& s, int& kb) {
-        if (c < nch_v) { s = 0; kb = c; }
-        else if (c < nch_v + nch_o) { s = 1; kb = c - nch_v; }
-        else if (c < 2 * nch_v + nch_o) { s = 2; kb = c - nch_v - nch_o; }
-        else { s = 3; kb = c - 2 * nch_v - nch_o; }
-    };
     const int64_t blk = (int64_t)n * ROWB;  // bytes of one chunk block (all n rows)
 
     // FP8 scale words: thread tid stages rows tid and tid + 256 (< NROW)
@@ -423,20 +417,46 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
         }
     }
 
+    // Chunk c of segment s lies (c - first chunk of s) blocks after the
+    // segment's first block: per segment, the Row and Col addresses of chunk
+    // 0 (of the whole loop) are formed once, so that a chunk's address is one
+    // selection by segment and one multiply-add.
+    const int seg1 = nch_v, seg2 = nch_v + nch_o, seg3 = 2 * nch_v + nch_o;
+    const char* rseg[4];
+    const char* cseg[4];
+    const uint32_t* rsseg[4];
+    const uint32_t* csseg[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const SegGeom sg = FORM == FORM_VIR ? seg_geom_vir(s, v, nch_v, nch_o, q, P, R, y)
+                                            : seg_geom(s, o, v, nch_v, nch_o, q, P, R, y);
+        const int first = s == 0 ? 0 : s == 1 ? seg1 : s == 2 ? seg2 : seg3;
+        rseg[s] = arr_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk - first) * blk;
+        cseg[s] = arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk - first) * blk;
+        if constexpr (PREC == 3) {
+            rsseg[s] = scale_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk - first) * (int64_t)n;
+            csseg[s] = scale_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk - first) * (int64_t)n;
+        }
+    }
+    // base of chunk c's segment as segment 0's base plus the steps between
+    // segment bases that c has passed (branch-free scalar selects)
+    auto pick = [&](int c, auto const (&a)[4]) {
+        const int64_t d1 = (const char*)a[1] - (const char*)a[0], d2 = (const char*)a[2] - (const char*)a[1],
+                      d3 = (const char*)a[3] - (const char*)a[2];
+        const int64_t d = (c >= seg1 ? d1 : 0) + (c >= seg2 ? d2 : 0) + (c >= seg3 ? d3 : 0);
+        return (std::remove_const_t<std::remove_reference_t<decltype(a[0])>>)((const char*)a[0] + d);
+    };
+
     u4 reg[NVEC];
     uint32_t sreg[NSROW];
     auto load = [&](int c) {
-        int s, kb;
-        chunk_seg(c, s, kb);
-        const SegGeom sg = FORM == FORM_VIR ? seg_geom_vir(s, v, nch_v, nch_o, q, P, R, y)
-                                            : seg_geom(s, o, v, nch_v, nch_o, q, P, R, y);
-        const char* rb = arr_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * blk;
-        const char* cb = arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * blk;
+        const char* rb = pick(c, rseg) + c * blk;
+        const char* cb = pick(c, cseg) + c * blk;
 #pragma unroll
         for (int e = 0; e < NVEC; ++e) reg[e] = *(const u4*)((isrow(e) ? rb : cb) + off[e]);
         if constexpr (PREC == 3) {
-            const uint32_t* rs = scale_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk + kb) * (int64_t)n;
-            const uint32_t* cs = scale_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk + kb) * (int64_t)n;
+            const uint32_t* rs = pick(c, rsseg) + c * (int64_t)n;
+            const uint32_t* cs = pick(c, csseg) + c * (int64_t)n;
 #pragma unroll
             for (int e = 0; e < NSROW; ++e) {
                 const int row = tid + e * NTHR;
