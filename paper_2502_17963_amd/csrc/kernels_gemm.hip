@@ -196,6 +196,79 @@ __device__ __forceinline__ void roles(int h, int i, int j, int k, int& q, int& P
     else { q = k; P = i; R = j; }
 }
 
+// The fragments of one staged chunk for one wave (FP64, FP32, split-BF16x3):
+// A fragments from LDS rows arow0 + 16 m + (lane % 16), B fragments from
+// rows brow0 + 16 n + (lane % 16), read by read() and multiplied by mfma(),
+// so that a caller can issue other work between the two.
+template <int PREC, int WB>
+struct StageFrags {
+    typedef typename Mode<PREC>::E E;
+    static constexpr int NS = (PREC == 0) ? 4 : 8;  // MFMA K-steps per stage
+    E af[WB][NS], bfr[WB][NS];
+    __device__ __forceinline__ void read(const char* L0, int arow0, int brow0, int fr, int fg) {
+#pragma unroll
+        for (int m = 0; m < WB; ++m) {
+            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+            const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
+            const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
+            const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
+            const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
+            const E* pa0 = (const E*)&a0; const E* pa1 = (const E*)&a1;
+            const E* pb0 = (const E*)&b0; const E* pb1 = (const E*)&b1;
+#pragma unroll
+            for (int s = 0; s < NS / 2; ++s) {
+                af[m][s] = pa0[s]; af[m][NS / 2 + s] = pa1[s];
+                bfr[m][s] = pb0[s]; bfr[m][NS / 2 + s] = pb1[s];
+            }
+        }
+    }
+    __device__ __forceinline__ void mfma(typename Mode<PREC>::Acc (&acc)[WB][WB]) const {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int m = 0; m < WB; ++m)
+#pragma unroll
+                for (int nn = 0; nn < WB; ++nn) {
+                    if constexpr (PREC == 0)
+                        acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m][s], bfr[nn][s], acc[m][nn], 0, 0, 0);
+                    else
+                        acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m][s], bfr[nn][s], acc[m][nn], 0, 0, 0);
+                }
+    }
+};
+// split-BF16x3: per accumulator lo*hi, then hi*lo, then hi*hi
+template <int WB>
+struct StageFrags<2, WB> {
+    bf8 ah[WB], al[WB], bh[WB], bl[WB];
+    __device__ __forceinline__ void read(const char* L0, int arow0, int brow0, int fr, int fg) {
+#pragma unroll
+        for (int m = 0; m < WB; ++m) {
+            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
+            ah[m] = *(const bf8*)(L0 + lds_off(ra, fg));
+            al[m] = *(const bf8*)(L0 + lds_off(ra, 4 + fg));
+            bh[m] = *(const bf8*)(L0 + lds_off(rb, fg));
+            bl[m] = *(const bf8*)(L0 + lds_off(rb, 4 + fg));
+        }
+    }
+    __device__ __forceinline__ void mfma(f4 (&acc)[WB][WB]) const {
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh[nn], acc[m][nn], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bl[nn], acc[m][nn], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < WB; ++m)
+#pragma unroll
+            for (int nn = 0; nn < WB; ++nn)
+                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh[nn], acc[m][nn], 0, 0, 0);
+    }
+};
+
 // The MFMA products of one staged chunk for one wave: WB x WB 16 x 16
 // blocks, A fragments from LDS rows arow0 + 16 m + (lane % 16), B fragments
 // from rows brow0 + 16 n + (lane % 16) of the stage at L0 (FP8: exponent
@@ -231,62 +304,10 @@ __device__ __forceinline__ void stage_products(typename Mode<PREC>::Acc (&acc)[W
             for (int nn = 0; nn < WB; ++nn)
                 acc[m][nn] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[m], bfr[nn], acc[m][nn], 0, 0,
                                                                               0, sa[m], 0, sb[nn]);
-    } else if constexpr (PREC == 2) {
-        bf8 ah[WB], al[WB], bh[WB], bl[WB];
-#pragma unroll
-        for (int m = 0; m < WB; ++m) {
-            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-            ah[m] = *(const bf8*)(L0 + lds_off(ra, fg));
-            al[m] = *(const bf8*)(L0 + lds_off(ra, 4 + fg));
-            bh[m] = *(const bf8*)(L0 + lds_off(rb, fg));
-            bl[m] = *(const bf8*)(L0 + lds_off(rb, 4 + fg));
-        }
-#pragma unroll
-        for (int m = 0; m < WB; ++m)
-#pragma unroll
-            for (int nn = 0; nn < WB; ++nn)
-                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[m], bh[nn], acc[m][nn], 0, 0, 0);
-#pragma unroll
-        for (int m = 0; m < WB; ++m)
-#pragma unroll
-            for (int nn = 0; nn < WB; ++nn)
-                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bl[nn], acc[m][nn], 0, 0, 0);
-#pragma unroll
-        for (int m = 0; m < WB; ++m)
-#pragma unroll
-            for (int nn = 0; nn < WB; ++nn)
-                acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[m], bh[nn], acc[m][nn], 0, 0, 0);
     } else {
-        constexpr int NS = (PREC == 0) ? 4 : 8;  // MFMA K-steps per stage
-        E af[WB][NS], bfr[WB][NS];
-#pragma unroll
-        for (int m = 0; m < WB; ++m) {
-            const int ra = arow0 + m * 16 + fr, rb = brow0 + m * 16 + fr;
-            const u4 a0 = *(const u4*)(L0 + lds_off(ra, fg));
-            const u4 a1 = *(const u4*)(L0 + lds_off(ra, 4 + fg));
-            const u4 b0 = *(const u4*)(L0 + lds_off(rb, fg));
-            const u4 b1 = *(const u4*)(L0 + lds_off(rb, 4 + fg));
-            const E* pa0 = (const E*)&a0; const E* pa1 = (const E*)&a1;
-            const E* pb0 = (const E*)&b0; const E* pb1 = (const E*)&b1;
-#pragma unroll
-            for (int s = 0; s < NS / 2; ++s) {
-                af[m][s] = pa0[s]; af[m][NS / 2 + s] = pa1[s];
-                bfr[m][s] = pb0[s]; bfr[m][NS / 2 + s] = pb1[s];
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-#pragma unroll
-            for (int m = 0; m < WB; ++m)
-#pragma unroll
-                for (int nn = 0; nn < WB; ++nn) {
-                    if constexpr (PREC == 0)
-                        acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[m][s], bfr[nn][s],
-                                                                           acc[m][nn], 0, 0, 0);
-                    else
-                        acc[m][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[m][s], bfr[nn][s],
-                                                                           acc[m][nn], 0, 0, 0);
-                }
+        StageFrags<PREC, WB> f;
+        f.read(L0, arow0, brow0, fr, fg);
+        f.mfma(acc);
     }
 }
 
@@ -325,6 +346,158 @@ __device__ __forceinline__ bool store_tile_fast(const Acc (&acc)[WB][WB], HT* ou
             for (int r = 0; r < 4; ++r)
                 *(HT*)(base + (roff[r] + m * mstep + nn * nstep)) = (HT)acc[m][nn][r];
     return true;
+}
+
+// The wave's tile of plane y of pair slot `pair` (triple t, pair h: 3 t + h)
+// into its blocked H buffer (layout in bqc_internal.h): the unmasked store
+// when the whole wave tile lies inside the plane, else element by element.
+template <class M, int WB, class Acc>
+__device__ __forceinline__ void store_plane_tile(const Acc (&acc)[WB][WB], void* hbuf, int n, int pair, int y,
+                                                 int u00, int w00, int wun, int wwn, int lane) {
+    typedef typename M::HT HT;
+    const int nt = ceil_div(n, EPI_T);
+    HT* out = (HT*)hbuf + (int64_t)pair * hpair_elems(n) + (int64_t)(y >> 3) * nt * nt * 512 + (y & 7) * 64;
+    if (store_tile_fast<M, WB>(acc, out, n, nt, u00, w00, wun, wwn, lane)) return;
+    const int fr = lane & 15;
+#pragma unroll
+    for (int m = 0; m < WB; ++m)
+#pragma unroll
+        for (int nn = 0; nn < WB; ++nn)
+            if (m < wun && nn < wwn) {
+                const int w = w00 + nn * 16 + fr;
+                const int wo = (w >> 3) * 512 + (w & 7);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int u = u00 + m * 16 + M::row(lane, r);
+                    if (u < n && w < n) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
+                }
+            }
+}
+
+// s_waitcnt immediate: vmcnt = vm (6 bits, split over [3:0] and [15:14]),
+// expcnt and lgkmcnt not waited on.
+constexpr int waitcnt_vm(int vm) { return (vm & 15) | (((vm >> 4) & 3) << 14) | (7 << 4) | (15 << 8); }
+
+// The work of logical work group L as h_gemm_body does it (loop over
+// occupied triples, split-BF16x3; measured slower than h_gemm_body for FP32,
+// over the register budget of two waves per SIMD for FP64, and FP8 rows
+// carry scale words), with the operands going from global memory straight into LDS
+// (global_load_lds_dwordx4: lane L of a wave writes the 16 bytes it loads at
+// the instruction's LDS base + 16 L, so each instruction fills eight
+// swizzled 128-byte rows, and the lane loads the 16-byte unit that belongs
+// at its LDS position).  Two LDS stages: after the barrier of chunk c every
+// wave reads its fragments of chunk c, issues the loads of chunk c + 1 into
+// the other stage (which every wave finished reading before that barrier)
+// and runs the MFMAs of chunk c; the barrier is preceded by a wait for the
+// wave's own loads only, without a memory fence.  Without staging registers
+// the compiler reads all of a chunk's fragments at once instead of block row
+// by block row.  Same operands, products, order and H as h_gemm_body.
+template <int PREC, class G>
+__device__ __forceinline__ void h_gemm_dma_body(const GemmLaunch& g, int L, int nblk, int ntile_u, int ntile_w) {
+    static_assert(PREC == 1 || PREC == 2, "FP32 or split-BF16x3 rows (no scale words, four-byte elements)");
+    constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, WB = G::WB;
+    constexpr int NW = NTHR / 64;       // waves
+    static_assert(TILE_U % 8 == 0 && NROW % (8 * NW) == 0, "whole eight-row pieces, evenly over the waves");
+    constexpr int NPW = NROW / 8 / NW;  // eight-row (1 KB) pieces per wave and chunk
+    static_assert(TILE_U % (NPW * 8) == 0, "a wave's pieces stay on one side");
+    static_assert(NPW < 64, "vmcnt holds the loads of one chunk");
+    typedef Mode<PREC> M;
+    typedef typename M::Acc Acc;
+    constexpr int KC = M::KC;
+
+    const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
+    const int n = v;
+    // uniform indices in scalar registers, as in h_gemm_body
+    int rem = L;
+    const int tw = __builtin_amdgcn_readfirstlane(rem % ntile_w); rem /= ntile_w;
+    const int tu = __builtin_amdgcn_readfirstlane(rem % ntile_u); rem /= ntile_u;
+    const int h = __builtin_amdgcn_readfirstlane(rem % 3); rem /= 3;
+    const int y = __builtin_amdgcn_readfirstlane(rem % n);
+    const int t = __builtin_amdgcn_readfirstlane(rem / n);
+    const int4 tr = g.trip[t];
+    int q, P, R;
+    roles(h, __builtin_amdgcn_readfirstlane(tr.x), __builtin_amdgcn_readfirstlane(tr.y),
+          __builtin_amdgcn_readfirstlane(tr.z), q, P, R);
+    int ub, un, wb, wn;
+    tile_range(tu, nblk, ntile_u, ub, un);
+    tile_range(tw, nblk, ntile_w, wb, wn);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wu = wave % G::WU, ww = wave / G::WU;
+    int wub, wun, wwb, wwn;
+    tile_range(wu, un, G::WU, wub, wun);
+    tile_range(ww, wn, G::WW, wwb, wwn);
+    const int arow0 = wub * 16, brow0 = TILE_U + wwb * 16;
+
+    __shared__ __attribute__((aligned(1024))) char lds[2][NROW * ROWB];
+
+    // The lane's source in each of the wave's pieces: LDS row `row`, 16-byte
+    // position `unit` holds unit unit ^ ((row >> 1) & 7) of the row (the
+    // swizzle of lds_off).  Rows past the operand's last row, or past the
+    // tile's blocks, read the operand's last row: their products land only
+    // in rows or columns of H that are not stored.
+    const bool srow = wave * NPW * 8 < TILE_U;  // the wave's pieces hold the Row factor
+    uint32_t soff[NPW];
+#pragma unroll
+    for (int p = 0; p < NPW; ++p) {
+        const int row = (wave * NPW + p) * 8 + (lane >> 3);
+        const int unit = lane & 7;
+        const int r = srow ? row : row - TILE_U;
+        const int gr = min((srow ? ub : wb) * 16 + r, n - 1);
+        soff[p] = (uint32_t)(gr * ROWB + ((unit ^ ((row >> 1) & 7)) << 4));
+    }
+
+    // the wave's factor at chunk 0 of the loop, per segment (chunk c of
+    // segment s lies c - (first chunk of s) blocks after the segment's
+    // first block)
+    const int nch_v = Kv / KC, nch_o = Ko / KC;
+    const int nch = 2 * nch_v + 2 * nch_o;
+    const int64_t blk = (int64_t)n * ROWB;
+    const int seg1 = nch_v, seg2 = nch_v + nch_o, seg3 = 2 * nch_v + nch_o;
+    const char* base[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const SegGeom sg = seg_geom(s, o, v, nch_v, nch_o, q, P, R, y);
+        const int first = s == 0 ? 0 : s == 1 ? seg1 : s == 2 ? seg2 : seg3;
+        base[s] = srow ? arr_base(g.ops, sg.arr_row) + (sg.row_mat * sg.nchunk - first) * blk
+                       : arr_base(g.ops, sg.arr_col) + (sg.col_mat * sg.nchunk - first) * blk;
+    }
+    const int64_t d1 = base[1] - base[0], d2 = base[2] - base[1], d3 = base[3] - base[2];
+    auto issue = [&](int c) {
+        const int64_t d = (c >= seg1 ? d1 : 0) + (c >= seg2 ? d2 : 0) + (c >= seg3 ? d3 : 0);
+        const char* src = base[0] + d + c * blk;
+        char* dst = lds[c & 1] + wave * NPW * 1024;
+#pragma unroll
+        for (int p = 0; p < NPW; ++p)
+            __builtin_amdgcn_global_load_lds((const void*)(src + soff[p]), dst + p * 1024, 16, 0, 0);
+    };
+    auto meet = [&]() {
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+
+    Acc acc[WB][WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+    const int fr = lane & 15, fg = lane >> 4;
+    issue(0);
+    for (int c = 0; c < nch; ++c) {
+        meet();
+        // all fragment reads first: the loads into the other stage are
+        // ordered after them (both touch LDS), and the MFMAs wait on the
+        // reads one by one
+        StageFrags<PREC, WB> f;
+        f.read(lds[c & 1], arow0, brow0, fr, fg);
+        if (c + 1 < nch) issue(c + 1);
+        f.mfma(acc);
+    }
+
+    store_plane_tile<M, WB>(acc, g.hbuf, n, t * 3 + h, y, (ub + wub) * 16, (wb + wwb) * 16, wun, wwn, lane);
 }
 
 template <int PREC, class G, int FORM>
@@ -494,25 +667,7 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
         __syncthreads();
     }
 
-    // H in EPI_T^3 blocks (layout in bqc_internal.h)
-    const int nt = ceil_div(n, EPI_T);
-    HT* out = (HT*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(n) +
-              (int64_t)(y >> 3) * nt * nt * 512 + (y & 7) * 64;
-    const int u00 = (ub + wub) * 16, w00 = (wb + wwb) * 16;
-    if (store_tile_fast<M, WB>(acc, out, n, nt, u00, w00, wun, wwn, lane)) return;
-#pragma unroll
-    for (int m = 0; m < WB; ++m)
-#pragma unroll
-        for (int nn = 0; nn < WB; ++nn)
-            if (m < wun && nn < wwn) {
-                const int w = w00 + nn * 16 + fr;
-                const int wo = (w >> 3) * 512 + (w & 7);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int u = u00 + m * 16 + M::row(lane, r);
-                    if (u < n && w < n) out[(int64_t)(u >> 3) * nt * 512 + (u & 7) * 8 + wo] = (HT)acc[m][nn][r];
-                }
-            }
+    store_plane_tile<M, WB>(acc, g.hbuf, n, t * 3 + h, y, (ub + wub) * 16, (wb + wwb) * 16, wun, wwn, lane);
 }
 
 template <int PREC, class G, int FORM>
@@ -523,7 +678,10 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_kernel(GemmLaunch g, int n_
     const int hw = blockIdx.x;
     const int L = (hw % 8) * per_xcd + hw / 8;
     if (L >= n_wg) return;
-    h_gemm_body<PREC, G, FORM>(g, L, nblk, ntile_u, ntile_w);
+    if constexpr (FORM == FORM_OCC && PREC == 2)
+        h_gemm_dma_body<PREC, G>(g, L, nblk, ntile_u, ntile_w);
+    else
+        h_gemm_body<PREC, G, FORM>(g, L, nblk, ntile_u, ntile_w);
 }
 
 // One contraction launch over several solves (fragments) at once: entry e
@@ -543,7 +701,10 @@ __global__ __launch_bounds__(G::NTHR, 1) void h_gemm_group_kernel(const GemmGrou
         else hi = mid - 1;
     }
     const GemmGroupEntry e = ent[lo];
-    h_gemm_body<PREC, G, FORM_OCC>(e.g, L - e.wg0, e.nblk, e.ntile_u, e.ntile_w);
+    if constexpr (PREC == 2)
+        h_gemm_dma_body<PREC, G>(e.g, L - e.wg0, e.nblk, e.ntile_u, e.ntile_w);
+    else
+        h_gemm_body<PREC, G, FORM_OCC>(e.g, L - e.wg0, e.nblk, e.ntile_u, e.ntile_w);
 }
 
 // The loop over virtual triples has small planes (n = nocc rows and
