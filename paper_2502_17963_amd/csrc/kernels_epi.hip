@@ -296,7 +296,7 @@ __device__ double block_sum_fixed(const double* x, int64_t n) {
     cs[threadIdx.x] = c;
     __syncthreads();
     for (int half = R_THREADS / 2; half >= 1; half >>= 1) {
-        if (threadIdx.x < half) {
+        if ((int)threadIdx.x < half) {
             double s1 = ss[threadIdx.x], c1 = cs[threadIdx.x];
             neu_add(s1, c1, ss[threadIdx.x + half]);
             c1 += cs[threadIdx.x + half];

@@ -276,7 +276,6 @@ struct StageFrags<2, WB> {
 template <int PREC, int WB>
 __device__ __forceinline__ void stage_products(typename Mode<PREC>::Acc (&acc)[WB][WB], const char* L0,
                                                const uint32_t* Ls, int arow0, int brow0, int fr, int fg) {
-    typedef typename Mode<PREC>::E E;
     if constexpr (PREC == 3) {
         // The FP8 16x16x128 MFMA reads lane group g's 32 bytes as
         // contraction elements [16g, 16g+16) and [64+16g, 64+16g+16) and
@@ -505,7 +504,6 @@ __device__ __forceinline__ void h_gemm_body(const GemmLaunch& g, int L, int nblk
     constexpr int TILE_U = G::TILE_U, NROW = G::NROW, NTHR = G::NTHR, NVEC = G::NVEC, WB = G::WB;
     typedef Mode<PREC> M;
     typedef typename M::Acc Acc;
-    typedef typename M::HT HT;
     constexpr int KC = M::KC;
 
     const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;

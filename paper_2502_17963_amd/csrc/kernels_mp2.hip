@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void segment_sum_kernel(const double* x, int64
     cs[threadIdx.x] = c;
     __syncthreads();
     for (int half = 128; half >= 1; half >>= 1) {
-        if (threadIdx.x < half) {
+        if ((int)threadIdx.x < half) {
             double s1 = ss[threadIdx.x], c1 = cs[threadIdx.x];
             neu(s1, c1, ss[threadIdx.x + half]);
             ss[threadIdx.x] = s1;
