@@ -845,6 +845,121 @@ __global__ __launch_bounds__(64 * PL_NP, 1) void h_gemm_planes_kernel(GemmLaunch
         }
 }
 
+// The work of h_gemm_planes_kernel for split-BF16x3 with the operands going from global
+// memory straight into two LDS stages, as h_gemm_dma_body does (the stage's
+// 8-row pieces are spread over the waves; a piece holds rows of the
+// plane-independent factor or of one plane's factor).  Rows past the
+// occupied space read its last row and planes past it read its last plane:
+// their products land only in rows, columns or planes of H that are not
+// stored.  Same operands, products, order and H as h_gemm_planes_kernel.
+template <int WB>
+__device__ __forceinline__ void h_gemm_planes_dma_body(const GemmLaunch& g, int L, int ngrp) {
+    constexpr int PREC = 2;
+    constexpr int NPAD = 16 * WB, NROW = (1 + PL_NP) * NPAD;
+    constexpr int NPIECE = NROW / 8;                       // eight-row (1 KB) pieces per stage
+    constexpr int NPW = (NPIECE + PL_NP - 1) / PL_NP;      // pieces per wave (the last may be absent)
+    static_assert(NPAD % 8 == 0, "a piece lies in one factor block");
+    typedef Mode<PREC> M;
+    constexpr int KC = M::KC;
+
+    const int o = g.o, v = g.v, Kv = g.ops.Kv, Ko = g.ops.Ko;
+    const int n = o;
+    int rem = L;
+    const int grp = __builtin_amdgcn_readfirstlane(rem % ngrp); rem /= ngrp;
+    const int h = __builtin_amdgcn_readfirstlane(rem % 3);
+    const int t = __builtin_amdgcn_readfirstlane(rem / 3);
+    const int4 tr = g.trip[t];
+    int B, A, C;  // middle virtual of the pair and the other two
+    roles(h, __builtin_amdgcn_readfirstlane(tr.x), __builtin_amdgcn_readfirstlane(tr.y),
+          __builtin_amdgcn_readfirstlane(tr.z), B, A, C);
+    const int y0 = grp * PL_NP;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    __shared__ __attribute__((aligned(1024))) char lds[2][NROW * ROWB];
+
+    f4 acc[WB][WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+        for (int b = 0; b < WB; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+    // piece k of this wave: piece wave + k PL_NP of the stage (uniform per wave)
+    uint32_t soff[NPW];
+    int pplane[NPW];  // -1: plane-independent factor, else the (clamped) plane
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+        const int pc = wave + k * PL_NP;
+        const int row = 8 * pc + (lane >> 3);  // LDS row
+        const int blkrow = (8 * pc) / NPAD;
+        const int r = min(row % NPAD, n - 1);
+        pplane[k] = blkrow == 0 ? -1 : min(y0 + blkrow - 1, n - 1);
+        soff[k] = (uint32_t)(r * ROWB + (((lane & 7) ^ ((row >> 1) & 7)) << 4));
+    }
+
+    const int nch_v = Kv / KC, nch_o = Ko / KC;
+    const int nch = 2 * nch_v + 2 * nch_o;
+    const int64_t blk = (int64_t)n * ROWB;  // bytes of one chunk block (all n rows)
+    auto seg_of = [&](int c) { return (c >= nch_v) + (c >= nch_v + nch_o) + (c >= 2 * nch_v + nch_o); };
+    auto issue = [&](int c) {
+        const int s = seg_of(c);
+        const int kb = c - (s == 0 ? 0 : s == 1 ? nch_v : s == 2 ? nch_v + nch_o : 2 * nch_v + nch_o);
+        // plane-independent matrix and the plane-y matrix y * v + X of this
+        // segment (the matrices of seg_geom_vir)
+        int arr_s, arr_y, X;
+        int64_t mat_s;
+        switch (s) {
+            case 0: arr_s = 0; mat_s = (int64_t)A * v + B; arr_y = 1; X = C; break;  // (uA|Bd) | t_wy^Cd
+            case 1: arr_s = 2; mat_s = (int64_t)B * v + C; arr_y = 3; X = A; break;  // t_lw^BC | -(uA|yl)
+            case 2: arr_s = 0; mat_s = (int64_t)C * v + B; arr_y = 1; X = A; break;  // (wC|Bd) | t_uy^Ad
+            default: arr_s = 2; mat_s = (int64_t)B * v + A; arr_y = 3; X = C; break;  // t_lu^BA | -(wC|yl)
+        }
+        const int nchunk = (s == 0 || s == 2) ? nch_v : nch_o;
+        const char* sb = arr_base(g.ops, arr_s) + (mat_s * nchunk + kb) * blk;
+        const char* yb = arr_base(g.ops, arr_y) + ((int64_t)X * nchunk + kb) * blk;
+        const int64_t ystep = (int64_t)v * nchunk * blk;  // next plane: matrix + v
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) {
+            const int pc = wave + k * PL_NP;
+            if (pc < NPIECE) {
+                const char* src = (pplane[k] < 0 ? sb : yb + pplane[k] * ystep) + soff[k];
+                __builtin_amdgcn_global_load_lds((const void*)src, lds[c & 1] + pc * 1024, 16, 0, 0);
+            }
+        }
+    };
+    auto meet = [&]() {
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+
+    const int fr = lane & 15, fg = lane >> 4;
+    const int own = NPAD * (1 + wave);  // first LDS row of this wave's plane factor
+    issue(0);
+    for (int c = 0; c < nch; ++c) {
+        meet();
+        const int s = seg_of(c);
+        const bool shared_row = (s == 0 || s == 3);  // the Row factor is the shared one
+        StageFrags<PREC, WB> f;
+        f.read(lds[c & 1], shared_row ? 0 : own, shared_row ? own : 0, fr, fg);
+        if (c + 1 < nch) issue(c + 1);
+        f.mfma(acc);
+    }
+
+    const int y = y0 + wave;
+    if (y >= n) return;
+    store_plane_tile<M, WB>(acc, g.hbuf, n, t * 3 + h, y, 0, 0, WB, WB, lane);
+}
+
+template <int WB>
+__global__ __launch_bounds__(64 * PL_NP, 1) void h_gemm_planes_dma_kernel(GemmLaunch g, int n_wg, int ngrp,
+                                                                          int per_xcd) {
+    const int hw = blockIdx.x;
+    const int L = (hw % 8) * per_xcd + hw / 8;  // XCD-aware order, as in h_gemm_kernel
+    if (L >= n_wg) return;
+    h_gemm_planes_dma_body<WB>(g, L, ngrp);
+}
+
 }  // namespace
 
 namespace {
@@ -882,7 +997,10 @@ KernelCall planes_call(const GemmLaunch& g) {
     const int n_wg = (int)n64;
     const int per_xcd = ceil_div(n_wg, 8);
     KernelCall k;
-    k.fn = (const void*)&h_gemm_planes_kernel<PREC, WB>;
+    if constexpr (PREC == 2)
+        k.fn = (const void*)&h_gemm_planes_dma_kernel<WB>;
+    else
+        k.fn = (const void*)&h_gemm_planes_kernel<PREC, WB>;
     k.grid = dim3(per_xcd * 8);
     k.block = dim3(64 * PL_NP);
     k.arg(g).arg(n_wg).arg(ngrp).arg(per_xcd);
