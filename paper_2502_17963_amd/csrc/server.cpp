@@ -127,6 +127,7 @@ struct bqc_server {
     bool stop = false;
     int callers = 0;                 // threads inside submit/poll/wait (destroy waits for them)
     std::map<uint64_t, std::pair<int, int>> faults;  // host-side tests: ticket -> (stage, code)
+    bool hold = false;               // host-side tests: admit nothing until released (or stopping)
     std::condition_variable cv_idle;
     uint64_t next_ticket = 1;
     hipStream_t check_stream = nullptr;  // reads device orbital energies at submit
@@ -338,7 +339,7 @@ void slot_main(bqc_server* s, int idx) {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
                 if (s->stop && s->queue.empty()) return;
-                grp = admit_group_locked(s);
+                if (!s->hold || s->stop) grp = admit_group_locked(s);
                 if (!grp.empty()) break;
                 s->cv_work.wait(lk);
             }
@@ -459,6 +460,14 @@ int server_callers(bqc_server* s) {
 void server_inject_fault(bqc_server* s, uint64_t ticket, int stage, int code) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->faults[ticket] = {stage, code};
+}
+
+// Host-side tests: while `on`, the slots admit no request (submitted ones
+// stay queued, so that a cancel meets them there); off lets them run.
+void server_hold_admission(bqc_server* s, bool on) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->hold = on;
+    if (!on) s->cv_work.notify_all();
 }
 
 namespace {

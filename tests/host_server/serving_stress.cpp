@@ -52,6 +52,7 @@
 namespace bqc {
 int server_callers(bqc_server* s);  // server.cpp: threads inside an entry point
 void server_inject_fault(bqc_server* s, uint64_t ticket, int stage, int code);  // server.cpp
+void server_hold_admission(bqc_server* s, bool on);                               // server.cpp
 }
 
 namespace {
@@ -313,6 +314,9 @@ int run_faults(int direct) {
     }
     struct Job { int o, v; std::vector<double> eo, ev, z; uint64_t t; int cancel_rc; };
     std::vector<Job> jobs(N);
+    // nothing is admitted until every request is submitted and the chosen
+    // ones are cancelled: those cancels meet queued requests
+    bqc::server_hold_admission(s, true);
     for (int n = 0; n < N; ++n) {
         Job& j = jobs[n];
         j.o = 4 + n % 9;
@@ -328,6 +332,7 @@ int run_faults(int direct) {
         }
         j.cancel_rc = n % 11 == 4 ? bqc_t_cancel(s, j.t) : 99;
     }
+    bqc::server_hold_admission(s, false);
     int bad = 0, cancelled = 0, enomem = 0, edevice = 0, ok = 0;
     for (int n = N - 1; n >= 0; --n) {  // consume in reverse order
         Job& j = jobs[n];
@@ -336,11 +341,10 @@ int run_faults(int direct) {
         int want = BQC_OK;  // the outcome had the request run
         if (n % 7 == 3) want = BQC_ENOMEM;
         else if (n % 7 == 5) want = BQC_EDEVICE;
-        if (j.cancel_rc != 99 && j.cancel_rc != BQC_OK && j.cancel_rc != BQC_PENDING) want = -100;
-        // a cancel that returned BQC_OK either removed the queued request
-        // (BQC_ECANCELED) or found it finished already (its own outcome)
-        const bool was_cancelled = j.cancel_rc == BQC_OK && rc == BQC_ECANCELED;
-        const bool good = was_cancelled || (rc == want && (rc != BQC_OK || e == expected_energy(j.o, j.eo)));
+        // every cancel met its request queued: it ends with BQC_ECANCELED
+        const bool good = j.cancel_rc == 99
+                              ? rc == want && (rc != BQC_OK || e == expected_energy(j.o, j.eo))
+                              : j.cancel_rc == BQC_OK && rc == BQC_ECANCELED;
         if (!good) {
             std::printf("faults: request %d rc %d (want %d) energy %.17g (want %.17g) cancel %d\n", n, rc, want, e,
                         expected_energy(j.o, j.eo), j.cancel_rc);
