@@ -373,9 +373,65 @@ __device__ __forceinline__ void store_plane_tile(const Acc (&acc)[WB][WB], void*
             }
 }
 
+
+// The unmasked store of store_tile_fast through a wave-private LDS region of
+// 4 WB 256-byte runs: block row m of the wave tile (16 x 16 WB elements) is
+// 4 WB runs of 8 x 8 elements (two 8-row groups times 2 WB 8-column groups),
+// each contiguous in the blocked H layout.  The lanes write their elements
+// into the runs in LDS, read them back 16 bytes at a time and store each run
+// with 16 lanes of 16-byte stores.  Word pos = 8 (u % 8) + w % 8 of run k
+// sits at pos ^ 8 (k & 1) ^ 16 (pos / 32) ^ 32 (k >= 2 WB): every 16-byte
+// group stays whole and in order, and the 64 lanes of one write meet 64
+// different banks (each half wave 32).  Same values at the same places as
+// store_tile_fast; false (nothing stored) when it would return false.  The
+// wave's LDS accesses stay in issue order, so no waits are needed between
+// the writes and the reads.  The stores are non-temporal: H is read once,
+// by a later kernel, and the operand rows that the other work groups re-read
+// keep the L2 to themselves.
+template <int WB>
+__device__ __forceinline__ bool store_tile_lds(const f4 (&acc)[WB][WB], float* out, int n, int nt, int u00, int w00,
+                                               int wun, int wwn, int lane, float* region) {
+    const int64_t rowblk = (int64_t)nt * 512;
+    const bool full = wun == WB && wwn == WB && u00 + 16 * WB <= n && w00 + 16 * WB <= n &&
+                      (int64_t)nt * nt * 512 * 4 < ((int64_t)1 << 31);
+    if (!full) return false;
+    const int fr = lane & 15, g = lane >> 4;
+    // write side: lane holds rows 4 g + r, column fr of each 16 x 16 block
+    const int wr_run = (g >> 1) * (2 * WB) + (fr >> 3);                 // run of block (m, 0)
+    const int wr_pos = (4 * (g & 1)) * 8 + (fr & 7);                    // pos at r = 0
+    const int wr_swz = 8 * (fr >> 3) + 16 * (g & 1) + 32 * (g >> 1);   // run parity follows fr / 8
+    // read side: lane takes 16-byte group j of run 4 k + lane / 16
+    const int j = lane & 15, rq = lane >> 4;
+    char* base = (char*)out;
+#pragma unroll
+    for (int m = 0; m < WB; ++m) {
+#pragma unroll
+        for (int nn = 0; nn < WB; ++nn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                region[(wr_run + 2 * nn) * 64 + ((wr_pos + 8 * r) ^ wr_swz)] = acc[m][nn][r];
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < WB; ++k) {
+            const int run = 4 * k + rq;
+            const int slot = (4 * j) ^ (8 * (run & 1)) ^ (16 * (j >> 3)) ^ (run >= 2 * WB ? 32 : 0);
+            const f4 val = *(const f4*)&region[run * 64 + slot];
+            const int u0 = u00 + 16 * m + 8 * (run / (2 * WB)), w0 = w00 + 8 * (run % (2 * WB));
+            const uint32_t off = (uint32_t)(((int64_t)(u0 >> 3) * rowblk + (int64_t)(w0 >> 3) * 512) * 4) + 16 * j;
+            __builtin_nontemporal_store(val, (f4*)(base + off));
+        }
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+    }
+    return true;
+}
+
 // s_waitcnt immediate: vmcnt = vm (6 bits, split over [3:0] and [15:14]),
 // expcnt and lgkmcnt not waited on.
 constexpr int waitcnt_vm(int vm) { return (vm & 15) | (((vm >> 4) & 3) << 14) | (7 << 4) | (15 << 8); }
+// s_waitcnt immediate: lgkmcnt = lgkm ([11:8]), vmcnt and expcnt not waited on.
+constexpr int waitcnt_lgkm(int lgkm) { return 15 | (3 << 14) | (7 << 4) | ((lgkm & 15) << 8); }
 
 // The work of logical work group L as h_gemm_body does it (loop over
 // occupied triples, split-BF16x3; measured slower than h_gemm_body for FP32,
@@ -390,7 +446,9 @@ constexpr int waitcnt_vm(int vm) { return (vm & 15) | (((vm >> 4) & 3) << 14) | 
 // and runs the MFMAs of chunk c; the barrier is preceded by a wait for the
 // wave's own loads only, without a memory fence.  Without staging registers
 // the compiler reads all of a chunk's fragments at once instead of block row
-// by block row.  Same operands, products, order and H as h_gemm_body.
+// by block row.  Same operands, products, order and H as h_gemm_body; a
+// wave tile that lies wholly inside the plane is stored through the freed
+// stage (store_tile_lds).
 template <int PREC, class G>
 __device__ __forceinline__ void h_gemm_dma_body(const GemmLaunch& g, int L, int nblk, int ntile_u, int ntile_w) {
     static_assert(PREC == 1 || PREC == 2, "FP32 or split-BF16x3 rows (no scale words, four-byte elements)");
@@ -496,6 +554,21 @@ __device__ __forceinline__ void h_gemm_dma_body(const GemmLaunch& g, int L, int 
         f.mfma(acc);
     }
 
+    // the store goes through the stage of chunk nch - 2: after every wave's
+    // own loads and fragment reads are done and this barrier, no load
+    // targets it and no wave still reads it
+    static_assert(NW * 4 * WB * 256 <= NROW * ROWB, "a store region per wave fits in one stage");
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(0) & waitcnt_lgkm(0));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    {
+        const int nt = ceil_div(n, EPI_T);
+        float* out = (float*)g.hbuf + (int64_t)(t * 3 + h) * hpair_elems(n) + (int64_t)(y >> 3) * nt * nt * 512 +
+                     (y & 7) * 64;
+        float* region = (float*)(lds[nch & 1] + wave * (4 * WB * 256));
+        if (store_tile_lds<WB>(acc, out, n, nt, (ub + wub) * 16, (wb + wwb) * 16, wun, wwn, lane, region)) return;
+    }
     store_plane_tile<M, WB>(acc, g.hbuf, n, t * 3 + h, y, (ub + wub) * 16, (wb + wwb) * 16, wun, wwn, lane);
 }
 
