@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="largest_fragment",
                     choices=["small", "large_fragment", "precision_sweep", "largest_fragment", "serving",
-                             "copy_calibration", "mp2", "small_fragments"])
+                             "copy_calibration", "mp2", "small_fragments", "serving_small"])
     ap.add_argument("--precisions", default="fp32,bf16x3,fp8",
                     help="comma list of candidate contraction precisions for the headline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference solve")
@@ -359,6 +359,67 @@ def run_small_fragments(args):
             f.write(line + "\n")
 
 
+def run_serving_small(args):
+    """The serving stream's small fragments (nocc <= 12; about 40 of its 256)
+    through the server (bqc_server_create, bqc_t_submit, bqc_t_poll):
+    split-BF16x3, 4 slots, grouped admission, host inputs (prepared before
+    the timed region and uploaded into the server's arena at admission,
+    inside it). Each round submits every request at once (closed loop) and
+    polls until all are done: requests per second per round, p50 / p99 of
+    the time from submit to the poll that saw the request done, and every
+    energy bitwise equal to the fragment's solve alone."""
+    import numpy as np
+
+    import paper_2502_17963_amd as bqc
+    from synth import flops_alg, make_inputs, serving_stream
+    prec = "bf16x3"
+    shapes = [s for s in serving_stream(256) if s["nocc"] <= 12]
+    xs = [make_inputs(sh["nocc"], sh["nvir"], sh["naux"], sh["seed"]) for sh in shapes]
+    alone = [bqc.t_energy(sh["nocc"], sh["nvir"], *x.arrays(), precision=prec) for sh, x in zip(shapes, xs)]
+    F = sum(flops_alg(sh["nocc"], sh["nvir"]) for sh in shapes)
+    steps = args.steps if args.steps is not None else 3
+    rounds, lat, same = [], [], True
+    with bqc.Server(precision=prec, max_inflight=4, mem_budget_bytes=16 << 30) as srv:
+        for r in range(max(args.warmup, 0) + steps):
+            t0 = time.perf_counter()
+            tickets = [srv.submit(sh["nocc"], sh["nvir"], *x.arrays()) for sh, x in zip(shapes, xs)]
+            t_sub = time.perf_counter()
+            done = {}
+            while len(done) < len(tickets):
+                for k, t in enumerate(tickets):
+                    if k in done:
+                        continue
+                    res = srv.poll(t)
+                    if res is not None:
+                        done[k] = (time.perf_counter(), res[0])
+                time.sleep(2e-4)
+            t1 = max(v[0] for v in done.values())
+            same = same and all(done[k][1] == alone[k] for k in range(len(tickets)))
+            if r >= args.warmup:
+                rounds.append(t1 - t0)
+                lat.extend(done[k][0] - t0 for k in range(len(tickets)))
+            print(f"[serving small] round {r}: {len(tickets)} requests in {(t1 - t0) * 1e3:.1f} ms "
+                  f"(submitted in {(t_sub - t0) * 1e3:.1f} ms)", file=sys.stderr, flush=True)
+    dt = float(np.median(rounds))
+    out = {"metric": "fragment req/s + p50/p99 latency, split-BF16x3, small fragments through the server",
+           "value": round(len(shapes) / dt, 2), "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+           "steps": steps, "warmup": args.warmup, "dtype": "bf16x3",
+           "data": "synthetic fragments of the serving stream's shape distribution, host inputs",
+           "config": {"workload": "serving_small", "requests": len(shapes), "closed_loop": True, "slots": 4,
+                      "grouped_admission": True, "nocc": sorted(set(sh["nocc"] for sh in shapes)),
+                      "nvir_range": [min(sh["nvir"] for sh in shapes), max(sh["nvir"] for sh in shapes)],
+                      "flops": F},
+           "round_s": [round(x, 5) for x in rounds], "tflops": round(F / dt / 1e12, 3),
+           "latency_s": {"p50": round(float(np.percentile(lat, 50)), 5),
+                         "p99": round(float(np.percentile(lat, 99)), 5), "max": round(float(max(lat)), 5)},
+           "bitwise_equal_alone": same, "hip_runtime_version": bqc.runtime_versions()}
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
 MP2_SHAPES = [(32, 300, 1000), (48, 480, 1600), (100, 1000, 3000)]
 
 
@@ -436,6 +497,8 @@ def main():
         return run_mp2(args)
     if args.workload == "small_fragments":
         return run_small_fragments(args)
+    if args.workload == "serving_small":
+        return run_serving_small(args)
     if args.sweep:
         return run_sweep(args)
     import numpy as np
