@@ -18,7 +18,10 @@ namespace {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Device memory the H buffers of one batch may take: 1.5 GiB (4 triples per
-// launch at nvir = 300; measured 2 % faster than 3 and no slower than 6).
+// launch at nvir = 300; measured 2 % faster than 3 and no slower than 6),
+// but at least two triples per launch while two fit in twice that (at
+// nvir = 480 a launch of one triple ends in a partial wave of work groups;
+// two per launch measured 2 % faster).
 constexpr int64_t kHBudget = (int64_t)3 << 29;
 
 struct Layout {
@@ -54,6 +57,7 @@ Layout layout(int o, int v, int precision, int form, bool fock) {
 int batch_triples(int o, int v, int precision, int form) {
     const int64_t per = 3 * hpair_elems(tile_space(o, v, form)) * hbuf_bytes(precision);
     int64_t nb = kHBudget / std::max<int64_t>(per, 1);
+    if (nb == 1) nb = 2;  // one triple's H fits the budget, two fit twice it
     nb = std::max<int64_t>(nb, 1);
     nb = std::min<int64_t>(nb, std::max<int64_t>(num_triples(triple_space(o, v, form)), 1));
     nb = std::min<int64_t>(nb, 4096);
